@@ -1,0 +1,12 @@
+"""Synch-EM for 2-D multi-reference alignment on AMD MI355X (gfx950).
+
+The EM iteration (plain full search and the windowed, prior-weighted form) runs in the HIP library
+``libsynchem.so`` built from ``csrc/``; this package is its thin Python binding:
+
+* ``binding.EM``            one EM problem resident on the GPU (em_init / em_step / queries)
+* ``binding.learn_prior``   histogram prior over the window from integer rotation errors
+* ``autograd.marginal_loglik``  differentiable marginal log-likelihood with a hand-written adjoint
+"""
+from .binding import EM, SynchemError, learn_prior, load  # noqa: F401
+
+__all__ = ["EM", "SynchemError", "learn_prior", "load"]

@@ -1,0 +1,121 @@
+// Internal interface between the host library (em_api.cpp) and the HIP kernels (em_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sem {
+
+enum Prec : int { P_F64 = 0, P_F32 = 1, P_BF16X3 = 2, P_F16 = 3, P_BF16 = 4 };
+
+// What one E(+M) pass does.
+enum PassFlags : int {
+    PF_ACC_M = 1,       // accumulate the M-step sums S, W_t and sum w*C into per-block partials
+    PF_STORE_LSE = 2,   // write the per-row log-sum-exp (checkpoint)
+    PF_LOAD_LSE = 4,    // normalise with the stored per-row log-sum-exp (adjoint recompute)
+    PF_QUERY = 8,       // write posterior rows, argmax and margin
+    PF_CHECK_STOP = 16  // return at once when the context's stop flag is set
+};
+
+enum FinMode : int { FIN_EM = 0, FIN_LL = 1, FIN_GRAD = 2 };
+
+constexpr int kThreads = 512;        // threads per workgroup of the E+M pass (8 wave64)
+constexpr int kMaxDPerThread = 4;    // D <= 4 * kThreads
+constexpr int kMaxD = kMaxDPerThread * kThreads;
+constexpr int kMaxWp = 1024;         // padded window <= 2 * kThreads
+constexpr int kMaxK = 512;
+constexpr int kStatsCap = 1024;
+
+// Bytes of one stored observation row (all planes), Dp reals wide.
+__host__ __device__ inline int64_t row_bytes(int prec, int Dp) {
+    switch (prec) {
+    case P_F64: return (int64_t)Dp * 8;
+    case P_F32: return (int64_t)Dp * 4;
+    case P_BF16X3: return (int64_t)Dp * 4;      // bf16 hi plane then bf16 lo plane
+    default: return (int64_t)Dp * 2;            // fp16 or bf16, one plane
+    }
+}
+
+struct PassArgs {
+    const uint8_t *V;          // N rows of rowbytes
+    int64_t rowbytes;
+    const float *rowscale;     // per-row factor undoing the storage scaling (null: 1)
+    const void *Thi, *Tlo;     // template, MFMA B-fragment order (see template_kernel)
+    const float *tscale;       // device scalar: factor undoing the template scaling
+    const float *logrho32;     // Wp, -inf on padding and on zero entries
+    const double *logrho64;
+    const float2 *E32;         // Wp x K: exp(+i k theta_i) (zero rows on padding)
+    const double2 *E64;
+    int64_t row_begin, row_end;
+    int D, K, Q, Dp, W, Wp;
+    double coef;               // 2 / sigma^2
+    int flags;
+    double *partials;          // [gridDim.x][ncols]
+    int ncols;
+    double *lse;               // per absolute row
+    float *post;               // (row - row_begin) x W
+    int32_t *argmax;
+    float *margin;
+    const int *stopped;
+};
+
+struct FinArgs {
+    int mode;
+    const double *red;         // reduced partials: S[2D], W[Wp], sum lse', sum w*C, rows
+    int64_t N;
+    int D, K, Q, W, Wp, L;
+    double sigma2, gamma, tol, g;
+    int update_rho;
+    double sum_vn2;            // sum_j ||v_j||^2 (FP64, from the unrounded observations)
+    const double *rho_bar;     // W
+    const double *gai;         // D or null
+    const double2 *phase;      // L: exp(+2 pi i m / L)
+    const double *a_in;        // 2D: the coefficients the pass used
+    const double *rho_in;      // W: the distribution the pass used
+    // FIN_EM: state update
+    double *a, *rho;
+    int64_t *t;
+    int *stopped;
+    double *ll_last;
+    double *stats;
+    float *logrho32;
+    double *logrho64;
+    // FIN_LL / FIN_GRAD outputs
+    double *out;               // [0] = log-likelihood, [1] = g * dLL/dsigma2
+    double *grad_a;            // 2D
+    double *grad_eta;          // W
+};
+
+struct TplArgs {
+    const double *a;
+    int D, K, Q, Dp, W, Wp, L, lo, prec;
+    const double2 *phase;
+    void *Thi, *Tlo;
+    float *tscale;
+    const int *stopped;
+};
+
+// Launchers (em_kernels.hip).  All return hipSuccess or the launch error.
+hipError_t launch_convert(int prec, const void *obs, int64_t N, int D, int Dp, uint8_t *V,
+                          int64_t rowbytes, float *rowscale, double *vnorm2, int *nonfinite,
+                          hipStream_t s);
+hipError_t launch_colsum(const void *obs, int is_c128, int64_t N, int D, double *partials,
+                         int G, hipStream_t s);
+hipError_t launch_reduce(const double *partials, int G, int ncols, double *out, hipStream_t s);
+hipError_t launch_scale(const double *in, double *out, int n, double factor, hipStream_t s);
+hipError_t launch_template(const TplArgs &a, hipStream_t s);
+hipError_t launch_pass(int prec, int BM, int WM, const PassArgs &a, int grid, size_t lds,
+                       hipStream_t s);
+hipError_t launch_finalize(const FinArgs &a, hipStream_t s);
+hipError_t launch_softmax(const double *eta, double *rho, float *logrho32, double *logrho64,
+                          int W, int Wp, hipStream_t s);
+hipError_t launch_logrho(const double *rho, float *logrho32, double *logrho64, int W, int Wp,
+                         hipStream_t s);
+hipError_t launch_histogram(const int32_t *err, int64_t n, int L, unsigned long long *counts,
+                            hipStream_t s);
+hipError_t pass_set_lds_limit(int prec, int BM, int WM, size_t lds);
+size_t pass_lds_bytes(int prec, int BM, int D, int K, int Dp, int Wp);
+hipError_t pass_occupancy(int prec, int BM, int WM, size_t lds, int *blocks_per_cu);
+const char *pass_kernel_name(int prec, int BM, int WM);
+bool pass_variant_exists(int prec, int BM, int WM);
+
+}  // namespace sem
