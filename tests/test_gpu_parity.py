@@ -1,6 +1,6 @@
 """GPU (HIP, through the C ABI) against the FP64 oracle on the same seeded inputs.
 
-Tolerances: FP64 path 1e-10 relative.  Low-precision paths: posteriors <= 1e-3 in max-abs and in
+Tolerances: FP64 path 1e-10 relative (posterior queries return float32, so 2e-7 there).  Low-precision paths: posteriors <= 1e-3 in max-abs and in
 Frobenius-relative error, estimate and log-likelihood relative error <= 1e-3 (tighter where the
 arithmetic allows); rotation argmax bit-exact on every row whose two best posteriors differ by
 more than 1e-3.  The single-plane bf16 mode is reported against a looser bar (5e-3): its rounding
@@ -15,7 +15,7 @@ import workloads as wl
 pytestmark = pytest.mark.gpu
 
 TOL = {  # posterior max-abs / frob-rel, estimate rel, loglik rel
-    "fp64": dict(post=1e-10, a=1e-10, ll=1e-12),
+    "fp64": dict(post=2e-7, a=1e-10, ll=1e-12),     # posteriors are returned as float32
     "fp32": dict(post=2e-4, a=2e-5, ll=1e-7),
     "bf16x3": dict(post=1e-3, a=1e-4, ll=1e-6),
     "fp16": dict(post=1e-3, a=2e-4, ll=1e-6),
@@ -103,7 +103,10 @@ def test_teacher_forced_step(gpu, prec, case):
     st = em.stats()
     assert st.shape == (1, 6)
     assert abs(st[0, 1] - ll_ref) <= TOL[prec]["ll"] * abs(ll_ref)
-    assert abs(st[0, 4] - it["stop"]) <= 1e-6 * abs(it["stop"]) + 1e-9 * np.vdot(a1, a1).real
+    # the stopping metric moves by at most ~2 sqrt(metric) ||delta a|| with the estimate's error
+    na = np.linalg.norm(a1)
+    bar = 3 * np.sqrt(it["stop"]) * TOL[prec]["a"] * na + 1e-12 * na * na
+    assert abs(st[0, 4] - it["stop"]) <= bar, (st[0, 4], it["stop"])
     em.close()
 
 
@@ -239,7 +242,7 @@ def test_full_size_windowed_step(gpu, prec):
     rb, _, _ = oracle.histogram_prior(wl.prior_error_draws(w, 0), w.L, lo, W)
     em = EM(_obs(V, prec, gpu), K=w.K, Q=w.Q, L=w.L, sigma2=s2, window=(lo, W), prior=rb,
             gamma=w.gamma, precision=prec)
-    a0 = V.mean(axis=0)
+    a0 = V.astype(np.complex64).astype(np.complex128).mean(axis=0)   # the GPU gets complex64
     a_g0 = em.state()[0]
     assert np.linalg.norm(a_g0 - a0) <= 1e-12 * np.linalg.norm(a0)
     for r0 in (0, 31_337, 99_000):
