@@ -1,0 +1,150 @@
+"""The hand-written adjoint of the marginal log-likelihood (em_loglik_fwd / em_loglik_bwd) and its
+torch.autograd.Function, against the oracle's Fisher-identity gradients and FP64 finite
+differences."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _fd_problem(W):
+    w = wl.WORKLOADS["c4fd"]
+    a_true = wl.image(w, 0)
+    V = wl.observations(w, 0, a=a_true)
+    lo = 0 if W == w.L else -(W // 2)
+    rng = np.random.default_rng(4)
+    eta = rng.standard_normal(W) * 0.3
+    a = V.mean(axis=0) + 0.05 * a_true
+    s2 = wl.noise_variance(a_true, w.snr) * 1.3
+    return w, V, lo, eta, a, s2
+
+
+def _rho(eta):
+    r = np.exp(eta - eta.max())
+    return r / r.sum()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 2e-4)])
+@pytest.mark.parametrize("W", [16, 7])
+def test_adjoint_matches_oracle_fisher_gradient(gpu, prec, tol, W):
+    import torch
+    from paper_2105_07372_amd import EM
+    w, V, lo, eta, a, s2 = _fd_problem(W)
+    obs = torch.from_numpy(V.astype(np.complex128 if prec == "fp64" else np.complex64)).to(gpu)
+    em = EM(obs, K=w.K, Q=w.Q, L=w.L, sigma2=s2, window=(lo, W), precision=prec)
+    a_d = torch.from_numpy(a).to(gpu)
+    eta_d = torch.from_numpy(eta).to(gpu)
+    ll = em.loglik_fwd(a_d, s2, eta_d)
+    ga = torch.empty_like(a_d)
+    ge = torch.empty_like(eta_d)
+    gs = em.loglik_bwd(1.0, ga, ge)
+    ll_o, ga_o, gs_o, ge_o = oracle.grad_loglik(V, a, s2, _rho(eta), w.kbar, w.L,
+                                                oracle.offsets(lo, W))
+    assert abs(ll - ll_o) <= tol * abs(ll_o)
+    assert np.linalg.norm(ga.cpu().numpy() - ga_o) <= tol * np.linalg.norm(ga_o) * 10
+    assert abs(gs - gs_o) <= tol * 10 * max(1.0, abs(gs_o))
+    assert np.abs(ge.cpu().numpy() - ge_o).max() <= tol * 10 * max(1.0, np.abs(ge_o).max())
+    em.close()
+
+
+def test_adjoint_against_gpu_finite_differences(gpu):
+    """FP64: central differences of the GPU log-likelihood itself against the GPU adjoint."""
+    import torch
+    from paper_2105_07372_amd import EM
+    w, V, lo, eta, a, s2 = _fd_problem(7)
+    em = EM(torch.from_numpy(V).to(gpu), K=w.K, Q=w.Q, L=w.L, sigma2=s2, window=(lo, 7),
+            precision="fp64")
+    ll = lambda a_, s_, e_: em.loglik_fwd(torch.from_numpy(a_).to(gpu), s_,
+                                          torch.from_numpy(e_).to(gpu))
+    ll(a, s2, eta)
+    ga = torch.empty(w.D, dtype=torch.complex128, device=gpu)
+    ge = torch.empty(7, dtype=torch.float64, device=gpu)
+    gs = em.loglik_bwd(1.0, ga, ge)
+    ga, ge = ga.cpu().numpy(), ge.cpu().numpy()
+    h = 1e-6 * float(np.abs(a).max())
+    for d in range(0, w.D, 5):
+        for unit, comp in ((1.0, ga[d].real), (1j, ga[d].imag)):
+            e = np.zeros(w.D, complex)
+            e[d] = unit * h
+            fd = (ll(a + e, s2, eta) - ll(a - e, s2, eta)) / (2 * h)
+            assert abs(fd - comp) <= 1e-6 * max(1.0, abs(comp))
+    hs = 1e-6 * s2
+    fd = (ll(a, s2 + hs, eta) - ll(a, s2 - hs, eta)) / (2 * hs)
+    assert abs(fd - gs) <= 1e-6 * max(1.0, abs(gs))
+    for i in range(7):
+        e = np.zeros(7)
+        e[i] = 1e-6
+        fd = (ll(a, s2, eta + e) - ll(a, s2, eta - e)) / 2e-6
+        assert abs(fd - ge[i]) <= 1e-5 * max(1.0, abs(ge[i]))
+    em.close()
+
+
+def test_autograd_function_and_fisher_step(gpu):
+    """torch.autograd through MarginalLogLik gives the adjoint's gradients, and a gradient-ascent
+    step of size sigma^2 / (2N) on a equals one EM coefficient update (no image prior)."""
+    import torch
+    from paper_2105_07372_amd import EM
+    from paper_2105_07372_amd.autograd import marginal_loglik
+    w, V, lo, eta, a, s2 = _fd_problem(16)
+    rho = _rho(eta)
+    em = EM(torch.from_numpy(V).to(gpu), K=w.K, Q=w.Q, L=w.L, sigma2=s2, window=(lo, 16),
+            prior=rho, precision="fp64", update_rho=False)
+    a_t = torch.from_numpy(a).to(gpu).requires_grad_(True)
+    s_t = torch.tensor(s2, dtype=torch.float64, device=gpu, requires_grad=True)
+    e_t = torch.from_numpy(eta).to(gpu).requires_grad_(True)
+    ll = marginal_loglik(em, a_t, s_t, e_t)
+    ga, gs, ge = torch.autograd.grad(3.0 * ll, (a_t, s_t, e_t))
+    ll_o, ga_o, gs_o, ge_o = oracle.grad_loglik(V, a, s2, rho, w.kbar, w.L, oracle.offsets(lo, 16))
+    assert abs(ll.item() - ll_o) <= 1e-10 * abs(ll_o)
+    assert np.linalg.norm(ga.cpu().numpy() - 3 * ga_o) <= 1e-9 * np.linalg.norm(ga_o)
+    assert abs(gs.item() - 3 * gs_o) <= 1e-9 * abs(gs_o)
+    assert np.abs(ge.cpu().numpy() - 3 * ge_o).max() <= 1e-9 * max(1.0, np.abs(ge_o).max())
+    # Fisher identity: a + s2/(2N) dLL/da == EM update at (a, rho)
+    em.set_state(a, rho, 0)
+    em.step(1)
+    a_em = em.state()[0]
+    a_step = a + s2 / (2 * w.N) * (ga.cpu().numpy() / 3.0)
+    assert np.linalg.norm(a_step - a_em) <= 1e-10 * np.linalg.norm(a_em)
+    em.close()
+
+
+def test_backward_needs_forward(gpu):
+    import torch
+    from paper_2105_07372_amd import EM, SynchemError
+    w, V, lo, eta, a, s2 = _fd_problem(16)
+    em = EM(torch.from_numpy(V).to(gpu), K=w.K, Q=w.Q, L=w.L, sigma2=s2, precision="fp64")
+    g = torch.empty(w.D, dtype=torch.complex128, device=gpu)
+    with pytest.raises(SynchemError) as ei:
+        em.loglik_bwd(1.0, g)
+    assert ei.value.status == -4
+    em.close()
+
+
+def test_adjoint_full_size_windowed(gpu):
+    """The differentiable log-likelihood on the windowed workload (N=1e5, D=512, W=49, FP32 with
+    FP64 reductions) at the state after 5 EM iterations: gradients against the oracle's."""
+    import torch
+    from paper_2105_07372_amd import EM
+    w = wl.WORKLOADS["c4"]
+    a_true = wl.image(w, 0)
+    V = wl.observations(w, 0, a=a_true)
+    s2 = wl.noise_variance(a_true, w.snr)
+    lo, W = w.window
+    rb, _, _ = oracle.histogram_prior(wl.prior_error_draws(w, 0), w.L, lo, W)
+    em = EM(torch.from_numpy(V.astype(np.complex64)).to(gpu), K=w.K, Q=w.Q, L=w.L, sigma2=s2,
+            window=(lo, W), prior=rb, gamma=w.gamma, precision="fp32")
+    em.step(5)
+    a5, rho5, _ = em.state()
+    a_d = torch.from_numpy(a5).to(gpu)
+    ll = em.loglik_fwd(a_d, s2 * 1.1)
+    ga = torch.empty_like(a_d)
+    gs = em.loglik_bwd(1.0, ga)
+    ll_o, ga_o, gs_o, _ = oracle.grad_loglik(V, a5, s2 * 1.1, rho5, w.kbar, w.L,
+                                             oracle.offsets(lo, W))
+    assert abs(ll - ll_o) <= 1e-6 * abs(ll_o)
+    assert np.linalg.norm(ga.cpu().numpy() - ga_o) <= 1e-3 * np.linalg.norm(ga_o)
+    assert abs(gs - gs_o) <= 1e-3 * abs(gs_o)
+    em.close()
