@@ -37,6 +37,9 @@ struct em_ctx {
     bool has_gai = false;
     // plan
     int BM = 0, WM = 0, grid = 0, ncols = 0, colsum_grid = 0;
+    int LD = 0;           // general pass: 1 = tile double-buffered by direct global-to-LDS copies
+    bool ks = false;      // K-split pass (template resident in registers)
+    int ksNT = 0, ksKSS = 0;
     int64_t rowbytes = 0;
     size_t lds = 0;
     hipStream_t stream = nullptr;
@@ -48,7 +51,7 @@ struct em_ctx {
     double sum_vn2 = 0;
     void *Thi = nullptr, *Tlo = nullptr, *ThiE = nullptr, *TloE = nullptr;
     float *tscale = nullptr, *tscaleE = nullptr;
-    float2 *E32 = nullptr;
+    float *E2 = nullptr;
     double2 *E64 = nullptr, *phase = nullptr;
     float *logrho32 = nullptr, *logrho32E = nullptr;
     double *logrho64 = nullptr, *logrho64E = nullptr;
@@ -121,20 +124,41 @@ int pow2_floor(int x) {
 
 // Choose rows per tile and the wave split of the pass for this problem.
 em_status plan(em_ctx *c, size_t lds_max) {
+    c->ks = false;
+    if (c->prec != P_F64 && c->prec != P_F32 && !(c->flags & EM_FLAG_GENERAL_PASS)) {
+        int BM = 0, NT = 0, KSS = 0;
+        if (ks_plan(c->prec, c->Dp, c->Wp, c->K, &BM, &NT, &KSS)) {
+            const size_t lds = ks_lds_bytes(c->prec, BM, NT, c->K, c->Dp, c->Wp);
+            if (lds <= lds_max && (int64_t)BM * c->K <= 16 * kThreads) {
+                c->ks = true;
+                c->BM = BM;
+                c->ksNT = NT;
+                c->ksKSS = KSS;
+                c->WM = 0;
+                c->lds = lds;
+                return EM_OK;
+            }
+        }
+    }
     const int cands_mfma[] = {64, 32, 16};
-    const int cands_f64[] = {32, 16};
+    const int cands_f64[] = {32, 16, 8};
     const int *cands = c->prec == P_F64 ? cands_f64 : cands_mfma;
-    const int ncand = c->prec == P_F64 ? 2 : 3;
+    const int ncand = 3;
     c->BM = 0;
-    for (int k = 0; k < ncand; ++k) {
-        const int BM = cands[k];
-        if ((int64_t)BM * c->rowbytes > 16 * kThreads * 16) continue;   // prefetch capacity
-        const size_t lds = pass_lds_bytes(c->prec, BM, c->D, c->K, c->Dp, c->Wp);
-        if (lds > lds_max) continue;
-        if (BM > 16 && (int64_t)BM / 2 >= c->N) continue;              // tiny N: small tiles
-        c->BM = BM;
-        c->lds = lds;
-        break;
+    // first choice: double-buffered tiles (rows of whole KiB), then register staging
+    for (int LD = (c->rowbytes % 1024 == 0) ? 1 : 0; LD >= 0 && !c->BM; --LD) {
+        for (int k = 0; k < ncand; ++k) {
+            const int BM = cands[k];
+            if (!LD && (int64_t)BM * c->rowbytes > (int64_t)kRegTileChunks * kThreads * 16) continue;
+            const size_t lds = pass_lds_bytes(c->prec, BM, c->K, c->Dp, c->Wp, LD);
+            if (lds > lds_max) continue;
+            if (BM > 16 && (int64_t)BM / 2 >= c->N) continue;          // tiny N: small tiles
+            if (BM < 16 && LD) continue;
+            c->BM = BM;
+            c->LD = LD;
+            c->lds = lds;
+            break;
+        }
     }
     if (!c->BM)
         return fail(c, EM_EUNSUPPORTED,
@@ -143,10 +167,10 @@ em_status plan(em_ctx *c, size_t lds_max) {
     const int NT = c->Wp / 16;
     const int WN = pow2_floor(NT < 8 ? NT : 8);
     int WM = 8 / WN;
-    if (WM > c->BM / 16) WM = c->BM / 16;
+    if (WM > c->BM / 16) WM = c->BM / 16 > 0 ? c->BM / 16 : 1;
     if (c->prec == P_F64) WM = 1;
     c->WM = WM;
-    if (!pass_variant_exists(c->prec, c->BM, c->WM))
+    if (!pass_variant_exists(c->prec, c->BM, c->WM, c->LD))
         return fail(c, EM_EUNSUPPORTED, "no pass variant for this tile shape");
     return EM_OK;
 }
@@ -166,7 +190,7 @@ em_status check_params(const em_params *p) {
         return fail(nullptr, EM_EINVAL, "update_rho must be 0 or 1");
     if (p->precision < EM_FP64 || p->precision > EM_BF16)
         return fail(nullptr, EM_EINVAL, "unknown precision");
-    if (p->flags & ~(uint64_t)(EM_FLAG_KEEP_LSE | EM_FLAG_TIMING))
+    if (p->flags & ~(uint64_t)(EM_FLAG_KEEP_LSE | EM_FLAG_TIMING | EM_FLAG_GENERAL_PASS))
         return fail(nullptr, EM_EINVAL, "unknown flag bits");
     if (p->window_lo < -(1 << 30) || p->window_lo > (1 << 30))
         return fail(nullptr, EM_EINVAL, "window_lo out of range");
@@ -211,11 +235,12 @@ void logrho_host(const std::vector<double> &rho, int Wp, std::vector<float> &l32
 }
 
 // One E(+M) pass over rows [r0, r1) with the given template / log-prior buffers.
-em_status run_pass(em_ctx *c, int flags, int64_t r0, int64_t r1, const void *Thi,
-                   const void *Tlo, const float *tscale, const float *lr32, const double *lr64,
-                   double coef, float *post, int32_t *argmax, float *margin, bool use_partials,
-                   bool timed) {
+em_status run_pass(em_ctx *c, int flags, int64_t r0, int64_t r1, const double *a,
+                   const void *Thi, const void *Tlo, const float *tscale, const float *lr32,
+                   const double *lr64, double coef, float *post, int32_t *argmax, float *margin,
+                   bool use_partials, bool timed) {
     PassArgs A{};
+    A.a = a;
     A.V = c->V;
     A.rowbytes = c->rowbytes;
     A.rowscale = c->rowscale;
@@ -224,7 +249,7 @@ em_status run_pass(em_ctx *c, int flags, int64_t r0, int64_t r1, const void *Thi
     A.tscale = tscale;
     A.logrho32 = lr32;
     A.logrho64 = lr64;
-    A.E32 = c->E32;
+    A.E2 = c->E2;
     A.E64 = c->E64;
     A.row_begin = r0;
     A.row_end = r1;
@@ -248,7 +273,10 @@ em_status run_pass(em_ctx *c, int flags, int64_t r0, int64_t r1, const void *Thi
     if (grid < 1) grid = 1;
     const bool ev = timed && c->timing && c->ev_used + 2 <= 2 * kTimingEvents;
     if (ev) HIPCHK(c, hipEventRecord(c->ev[c->ev_used], c->stream));
-    HIPCHK(c, launch_pass(c->prec, c->BM, c->WM, A, grid, c->lds, c->stream));
+    if (c->ks)
+        HIPCHK(c, launch_pass_ks(c->prec, c->BM, c->ksNT, c->ksKSS, A, grid, c->lds, c->stream));
+    else
+        HIPCHK(c, launch_pass(c->prec, c->BM, c->WM, c->LD, A, grid, c->lds, c->stream));
     if (ev) {
         HIPCHK(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
         c->ev_used += 2;
@@ -388,11 +416,18 @@ em_status em_init(em_ctx **out, const em_params *p, const void *obs_dev, const d
         return bail(EM_EDEVICE);
     }
     if ((st = plan(c, (size_t)ldsmax)) != EM_OK) return bail(st);
-    if (pass_set_lds_limit(c->prec, c->BM, c->WM, c->lds) != hipSuccess) (void)hipGetLastError();
     int occ = 1;
-    if (pass_occupancy(c->prec, c->BM, c->WM, c->lds, &occ) != hipSuccess || occ < 1) {
-        (void)hipGetLastError();
-        occ = 1;
+    if (c->ks) {
+        if (pass_ks_setup(c->prec, c->BM, c->ksNT, c->ksKSS, c->lds, &occ) != hipSuccess ||
+            occ < 1) {
+            (void)hipGetLastError();
+            occ = 1;
+        }
+    } else {
+        if (pass_setup(c->prec, c->BM, c->WM, c->LD, c->lds, &occ) != hipSuccess || occ < 1) {
+            (void)hipGetLastError();
+            occ = 1;
+        }
     }
     const int64_t ntiles = (c->N + c->BM - 1) / c->BM;
     const int64_t gmax = (int64_t)cus * occ;
@@ -410,7 +445,7 @@ em_status em_init(em_ctx **out, const em_params *p, const void *obs_dev, const d
         if ((st = dev_alloc(c, pp, tbytes)) != EM_OK) return bail(st);
     if ((st = alloc_t(c, &c->tscale, 4)) != EM_OK) return bail(st);
     if ((st = alloc_t(c, &c->tscaleE, 4)) != EM_OK) return bail(st);
-    if ((st = alloc_t(c, &c->E32, (size_t)c->Wp * c->K)) != EM_OK) return bail(st);
+    if ((st = alloc_t(c, &c->E2, (size_t)c->Wp * 2 * c->K)) != EM_OK) return bail(st);
     if ((st = alloc_t(c, &c->E64, (size_t)c->Wp * c->K)) != EM_OK) return bail(st);
     if ((st = alloc_t(c, &c->phase, (size_t)c->L)) != EM_OK) return bail(st);
     if ((st = alloc_t(c, &c->logrho32, (size_t)c->Wp)) != EM_OK) return bail(st);
@@ -448,13 +483,14 @@ em_status em_init(em_ctx **out, const em_params *p, const void *obs_dev, const d
         const long double ang = 2.0L * 3.14159265358979323846264338327950288L * m / c->L;
         ph[m] = make_double2((double)cosl(ang), (double)sinl(ang));
     }
-    std::vector<float2> e32((size_t)c->Wp * c->K, make_float2(0.f, 0.f));
+    std::vector<float> e2((size_t)c->Wp * 2 * c->K, 0.f);
     std::vector<double2> e64((size_t)c->Wp * c->K, make_double2(0.0, 0.0));
     for (int i = 0; i < c->W; ++i)
         for (int k = 0; k < c->K; ++k) {
             const int64_t m = ((int64_t)k * (c->lo + i)) % c->L;
             e64[(size_t)i * c->K + k] = ph[m];
-            e32[(size_t)i * c->K + k] = make_float2((float)ph[m].x, (float)ph[m].y);
+            e2[(size_t)i * 2 * c->K + k] = (float)ph[m].x;
+            e2[(size_t)i * 2 * c->K + c->K + k] = (float)ph[m].y;
         }
     std::vector<float> l32;
     std::vector<double> l64;
@@ -475,7 +511,7 @@ em_status em_init(em_ctx **out, const em_params *p, const void *obs_dev, const d
         }                                                                                      \
     } while (0)
     UP(c->phase, ph.data(), ph.size() * sizeof(double2));
-    UP(c->E32, e32.data(), e32.size() * sizeof(float2));
+    UP(c->E2, e2.data(), e2.size() * sizeof(float));
     UP(c->E64, e64.data(), e64.size() * sizeof(double2));
     UP(c->rho, rho0.data(), rho0.size() * 8);
     UP(c->rho_bar, rho0.data(), rho0.size() * 8);
@@ -550,12 +586,13 @@ em_status em_step(em_ctx *c, int32_t n_iter, double tol, int32_t *iters_done, do
     FinArgs F = fin_base(c, FIN_EM);
     F.tol = tol;
     for (int it = 0; it < n_iter; ++it) {
-        em_status st = run_pass(c, flags, 0, c->N, c->Thi, c->Tlo, c->tscale, c->logrho32,
+        em_status st = run_pass(c, flags, 0, c->N, c->a, c->Thi, c->Tlo, c->tscale, c->logrho32,
                                 c->logrho64, coef, nullptr, nullptr, nullptr, true, true);
         if (st != EM_OK) return st;
         HIPCHK(c, launch_reduce(c->partials, c->grid, c->ncols, c->red, c->stream));
         HIPCHK(c, launch_finalize(F, c->stream));
-        if ((st = run_template(c, c->a, c->Thi, c->Tlo, c->tscale, true)) != EM_OK) return st;
+        if (!c->ks)      // the K-split pass builds its template from a_t itself
+            if ((st = run_template(c, c->a, c->Thi, c->Tlo, c->tscale, true)) != EM_OK) return st;
     }
     if (iters_done || ll_last) {
         int64_t t1 = 0;
@@ -572,7 +609,7 @@ em_status em_step(em_ctx *c, int32_t n_iter, double tol, int32_t *iters_done, do
 em_status em_loglik(em_ctx *c, double *ll) {
     if (!c) return fail(nullptr, EM_EINVAL, "ctx is NULL");
     if (!ll) return fail(c, EM_EINVAL, "ll is NULL");
-    em_status st = run_pass(c, 0, 0, c->N, c->Thi, c->Tlo, c->tscale, c->logrho32, c->logrho64,
+    em_status st = run_pass(c, 0, 0, c->N, c->a, c->Thi, c->Tlo, c->tscale, c->logrho32, c->logrho64,
                             2.0 / c->sigma2, nullptr, nullptr, nullptr, true, false);
     if (st != EM_OK) return st;
     HIPCHK(c, launch_reduce(c->partials, c->grid, c->ncols, c->red, c->stream));
@@ -588,7 +625,7 @@ em_status em_posterior(em_ctx *c, int64_t row0, int64_t nrows, float *w_dev, int
     if (row0 < 0 || nrows < 0 || row0 + nrows > c->N)
         return fail(c, EM_EINVAL, "row range outside [0, N)");
     if (nrows == 0) return EM_OK;
-    return run_pass(c, PF_QUERY, row0, row0 + nrows, c->Thi, c->Tlo, c->tscale, c->logrho32,
+    return run_pass(c, PF_QUERY, row0, row0 + nrows, c->a, c->Thi, c->Tlo, c->tscale, c->logrho32,
                     c->logrho64, 2.0 / c->sigma2, w_dev, argmax_dev, margin_dev, false, false);
 }
 
@@ -644,7 +681,7 @@ em_status em_loglik_fwd(em_ctx *c, const double *a_dev, double sigma2, const dou
     }
     em_status st = run_template(c, c->aE, c->ThiE, c->TloE, c->tscaleE, false);
     if (st != EM_OK) return st;
-    st = run_pass(c, PF_STORE_LSE, 0, c->N, c->ThiE, c->TloE, c->tscaleE, c->logrho32E,
+    st = run_pass(c, PF_STORE_LSE, 0, c->N, c->aE, c->ThiE, c->TloE, c->tscaleE, c->logrho32E,
                   c->logrho64E, 2.0 / sigma2, nullptr, nullptr, nullptr, true, false);
     if (st != EM_OK) return st;
     HIPCHK(c, launch_reduce(c->partials, c->grid, c->ncols, c->red, c->stream));
@@ -667,7 +704,7 @@ em_status em_loglik_bwd(em_ctx *c, double g, double *grad_a_dev, double *grad_si
     if (!c->fwd_valid) return fail(c, EM_ESTATE, "em_loglik_bwd needs a preceding em_loglik_fwd");
     if (!grad_a_dev) return fail(c, EM_EINVAL, "grad_a_dev is NULL");
     if (!std::isfinite(g)) return fail(c, EM_EINVAL, "g must be finite");
-    em_status st = run_pass(c, PF_ACC_M | PF_LOAD_LSE, 0, c->N, c->ThiE, c->TloE, c->tscaleE,
+    em_status st = run_pass(c, PF_ACC_M | PF_LOAD_LSE, 0, c->N, c->aE, c->ThiE, c->TloE, c->tscaleE,
                             c->logrho32E, c->logrho64E, 2.0 / c->sigma2E, nullptr, nullptr,
                             nullptr, true, false);
     if (st != EM_OK) return st;
@@ -773,7 +810,9 @@ em_status em_get_info(const em_ctx *c, em_info *info) {
     info->window_padded = c->Wp;
     info->bytes_per_row = c->rowbytes;
     info->lds_bytes = (int64_t)c->lds;
-    std::snprintf(info->kernel, sizeof info->kernel, "%s", pass_kernel_name(c->prec, c->BM, c->WM));
+    std::snprintf(info->kernel, sizeof info->kernel, "%s",
+                  c->ks ? pass_ks_name(c->prec, c->BM, c->ksNT, c->ksKSS)
+                        : pass_kernel_name(c->prec, c->BM, c->WM, c->LD));
     return EM_OK;
 }
 

@@ -24,6 +24,7 @@ constexpr int kMaxD = kMaxDPerThread * kThreads;
 constexpr int kMaxWp = 1024;         // padded window <= 2 * kThreads
 constexpr int kMaxK = 512;
 constexpr int kStatsCap = 1024;
+constexpr int kRegTileChunks = 8;    // register-staged tiles: <= 8 x 16 B per thread (64 KiB)
 
 // Bytes of one stored observation row (all planes), Dp reals wide.
 __host__ __device__ inline int64_t row_bytes(int prec, int Dp) {
@@ -36,6 +37,7 @@ __host__ __device__ inline int64_t row_bytes(int prec, int Dp) {
 }
 
 struct PassArgs {
+    const double *a;           // 2D: the coefficients (the K-split pass builds its template)
     const uint8_t *V;          // N rows of rowbytes
     int64_t rowbytes;
     const float *rowscale;     // per-row factor undoing the storage scaling (null: 1)
@@ -43,8 +45,8 @@ struct PassArgs {
     const float *tscale;       // device scalar: factor undoing the template scaling
     const float *logrho32;     // Wp, -inf on padding and on zero entries
     const double *logrho64;
-    const float2 *E32;         // Wp x K: exp(+i k theta_i) (zero rows on padding)
-    const double2 *E64;
+    const float *E2;           // Wp x 2K: [Re exp(+i k theta_i) | Im ...] (zero rows on padding)
+    const double2 *E64;        // Wp x K: exp(+i k theta_i), FP64 path
     int64_t row_begin, row_end;
     int D, K, Q, Dp, W, Wp;
     double coef;               // 2 / sigma^2
@@ -103,7 +105,7 @@ hipError_t launch_colsum(const void *obs, int is_c128, int64_t N, int D, double 
 hipError_t launch_reduce(const double *partials, int G, int ncols, double *out, hipStream_t s);
 hipError_t launch_scale(const double *in, double *out, int n, double factor, hipStream_t s);
 hipError_t launch_template(const TplArgs &a, hipStream_t s);
-hipError_t launch_pass(int prec, int BM, int WM, const PassArgs &a, int grid, size_t lds,
+hipError_t launch_pass(int prec, int BM, int WM, int LD, const PassArgs &a, int grid, size_t lds,
                        hipStream_t s);
 hipError_t launch_finalize(const FinArgs &a, hipStream_t s);
 hipError_t launch_softmax(const double *eta, double *rho, float *logrho32, double *logrho64,
@@ -112,10 +114,15 @@ hipError_t launch_logrho(const double *rho, float *logrho32, double *logrho64, i
                          hipStream_t s);
 hipError_t launch_histogram(const int32_t *err, int64_t n, int L, unsigned long long *counts,
                             hipStream_t s);
-hipError_t pass_set_lds_limit(int prec, int BM, int WM, size_t lds);
-size_t pass_lds_bytes(int prec, int BM, int D, int K, int Dp, int Wp);
-hipError_t pass_occupancy(int prec, int BM, int WM, size_t lds, int *blocks_per_cu);
-const char *pass_kernel_name(int prec, int BM, int WM);
-bool pass_variant_exists(int prec, int BM, int WM);
+size_t pass_lds_bytes(int prec, int BM, int K, int Dp, int Wp, int LD);
+hipError_t pass_setup(int prec, int BM, int WM, int LD, size_t lds, int *blocks_per_cu);
+const char *pass_kernel_name(int prec, int BM, int WM, int LD);
+bool pass_variant_exists(int prec, int BM, int WM, int LD);
+bool ks_plan(int prec, int Dp, int Wp, int K, int *BM, int *NT, int *KSS);
+size_t ks_lds_bytes(int prec, int BM, int NT, int K, int Dp, int Wp);
+hipError_t launch_pass_ks(int prec, int BM, int NT, int KSS, const PassArgs &a, int grid,
+                          size_t lds, hipStream_t s);
+hipError_t pass_ks_setup(int prec, int BM, int NT, int KSS, size_t lds, int *blocks_per_cu);
+const char *pass_ks_name(int prec, int BM, int NT, int KSS);
 
 }  // namespace sem

@@ -16,6 +16,8 @@
 #include <math.h>
 #include <stdio.h>
 
+#include <type_traits>
+
 namespace sem {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -184,6 +186,7 @@ __global__ __launch_bounds__(512) void reduce_kernel(const double *partials, int
     const int col = blockIdx.x * 64 + cl;
     double s = 0.0;
     if (col < ncols) {
+#pragma unroll 8
         for (int b = gs; b < G; b += 8) s += partials[(int64_t)b * ncols + col];
     }
     sh[gs][cl] = s;
@@ -318,22 +321,25 @@ template <> struct PT<P_F64> {
 
 __host__ __device__ constexpr int align_up(int x, int a) { return (x + a - 1) / a * a; }
 
-// LDS layout of the pass: [V tile: BM x RS bytes][C tile: BM x CSW][U chunk: UR x K][row factors]
-constexpr int kUR = 16;                           // rows per U / M-step chunk
+// LDS layout of the pass: [V tile(s): nbuf x BM x RS bytes][C tile: BM x CSW][U tile: BM x K]
+// [row factors: BM x 2].  nbuf = 2 when the tile is double-buffered by direct global-to-LDS
+// copies.
 struct PassLds {
     int RS, CSW;
-    int off_c, off_u, off_f, total;
+    int off_v1, off_c, off_u, off_f, off_lr, total;
 };
-__host__ __device__ inline PassLds pass_lds(int prec, int BM, int K, int Dp, int Wp) {
+__host__ __device__ inline PassLds pass_lds(int prec, int BM, int K, int Dp, int Wp, int nbuf) {
     PassLds l;
     const int rb = (int)row_bytes(prec, Dp);
     const int cs = prec == P_F64 ? 8 : 4;
     l.RS = rb + 16;
     l.CSW = Wp + 1;
-    l.off_c = align_up(BM * l.RS, 16);
+    l.off_v1 = align_up(BM * l.RS, 16);
+    l.off_c = align_up(nbuf * BM * l.RS, 16);
     l.off_u = align_up(l.off_c + BM * l.CSW * cs, 16);
-    l.off_f = align_up(l.off_u + kUR * K * 2 * cs, 16);
-    l.total = l.off_f + BM * 8 + 16;
+    l.off_f = align_up(l.off_u + BM * K * 2 * cs, 16);
+    l.off_lr = align_up(l.off_f + 2 * BM * cs, 16);
+    l.total = l.off_lr + Wp * 4 + 16;
     return l;
 }
 
@@ -357,121 +363,147 @@ __device__ __forceinline__ typename PT<P>::CT2 load_v(const uint8_t *row, int d,
     }
 }
 
-// GEMM of one n-tile for MSW m-subtiles (rows ms*16 .. +15, ms = wm + m*WM), MFMA paths.
-template <int P, int MSW, int WM>
-__device__ __forceinline__ void gemm_ntile(f32x4 (&acc)[MSW], const uint8_t *Vs, int RS, int wm,
-                                           int lane, int nt, int Dp, const void *Thi,
-                                           const void *Tlo) {
+// Correlations of MSW 16-row blocks (rows (wm + m WM) 16 ..) with up to NTW 16-column tiles
+// (nt0, nt0 + WN, ...) of the template, MFMA paths.  A fragments come from the LDS tile, B
+// fragments stream from L2 through a ring of PD k-steps in registers.
+template <int P, int MSW, int WM, int NTW, int PD>
+__device__ __forceinline__ void gemm_ntiles(f32x4 (&acc)[NTW][MSW], const uint8_t *Vs, int RS,
+                                            int wm, int lane, int nt0, int WN, int NT, int Dp,
+                                            const void *Thi, const void *Tlo) {
     const int g = lane >> 4, rl = lane & 15;
+    bool ok[NTW];
 #pragma unroll
-    for (int m = 0; m < MSW; ++m) acc[m] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    for (int n = 0; n < NTW; ++n) {
+        ok[n] = nt0 + n * WN < NT;
+#pragma unroll
+        for (int m = 0; m < MSW; ++m) acc[n][m] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    }
+    const uint8_t *Arow[MSW];
+#pragma unroll
+    for (int m = 0; m < MSW; ++m) Arow[m] = Vs + ((wm + m * WM) * 16 + rl) * RS + g * 16;
     if constexpr (P == P_F32) {
         const int KG = Dp / 16;
-        const float4 *B = (const float4 *)Thi + (int64_t)nt * KG * 64 + lane;
-        const uint8_t *Arow[MSW];
+        const float4 *B[NTW];
+        float4 b[PD][NTW];
 #pragma unroll
-        for (int m = 0; m < MSW; ++m) Arow[m] = Vs + ((wm + m * WM) * 16 + rl) * RS + g * 16;
-        float4 b = B[0];
-#pragma unroll 2
-        for (int kg = 0; kg < KG; ++kg) {
-            const float4 bn = (kg + 1 < KG) ? B[(kg + 1) * 64] : b;
+        for (int n = 0; n < NTW; ++n) B[n] = (const float4 *)Thi + (int64_t)(nt0 + n * WN) * KG * 64 + lane;
 #pragma unroll
-            for (int m = 0; m < MSW; ++m) {
-                const float4 a = *(const float4 *)(Arow[m] + kg * 64);
-                acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc[m], 0, 0, 0);
-                acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc[m], 0, 0, 0);
-                acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc[m], 0, 0, 0);
-                acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc[m], 0, 0, 0);
+        for (int u = 0; u < PD; ++u)
+#pragma unroll
+            for (int n = 0; n < NTW; ++n)
+                if (ok[n] && u < KG) b[u][n] = B[n][u * 64];
+        for (int kg0 = 0; kg0 < KG; kg0 += PD) {
+#pragma unroll
+            for (int u = 0; u < PD; ++u) {
+                const int kg = kg0 + u;
+                if (kg >= KG) break;
+                float4 a[MSW];
+#pragma unroll
+                for (int m = 0; m < MSW; ++m) a[m] = *(const float4 *)(Arow[m] + kg * 64);
+#pragma unroll
+                for (int n = 0; n < NTW; ++n) {
+                    if (!ok[n]) continue;
+                    const float4 bb = b[u][n];
+#pragma unroll
+                    for (int m = 0; m < MSW; ++m) {
+                        acc[n][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m].x, bb.x, acc[n][m], 0, 0, 0);
+                        acc[n][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m].y, bb.y, acc[n][m], 0, 0, 0);
+                        acc[n][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m].z, bb.z, acc[n][m], 0, 0, 0);
+                        acc[n][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m].w, bb.w, acc[n][m], 0, 0, 0);
+                    }
+                    if (kg + PD < KG) b[u][n] = B[n][(kg + PD) * 64];
+                }
             }
-            b = bn;
         }
     } else {
         const int KS = Dp / 32;
-        const uint4 *Bh = (const uint4 *)Thi + (int64_t)nt * KS * 64 + lane;
-        const uint4 *Bl = (const uint4 *)Tlo + (int64_t)nt * KS * 64 + lane;
-        const uint8_t *Arow[MSW];
+        const u32x4 *Bh[NTW], *Bl[NTW];
+        u32x4 bh[PD][NTW], bl[PD][NTW];
 #pragma unroll
-        for (int m = 0; m < MSW; ++m) Arow[m] = Vs + ((wm + m * WM) * 16 + rl) * RS + g * 16;
-        uint4 bh = Bh[0], bl = Bl[0];
-#pragma unroll 2
-        for (int ks = 0; ks < KS; ++ks) {
-            uint4 bhn = bh, bln = bl;
-            if (ks + 1 < KS) {
-                bhn = Bh[(ks + 1) * 64];
-                bln = Bl[(ks + 1) * 64];
-            }
+        for (int n = 0; n < NTW; ++n) {
+            Bh[n] = (const u32x4 *)Thi + (int64_t)(nt0 + n * WN) * KS * 64 + lane;
+            Bl[n] = (const u32x4 *)Tlo + (int64_t)(nt0 + n * WN) * KS * 64 + lane;
+        }
 #pragma unroll
-            for (int m = 0; m < MSW; ++m) {
-                const uint4 ah = *(const uint4 *)(Arow[m] + ks * 64);
-                if constexpr (P == P_F16) {
-                    f16x8 A8 = __builtin_bit_cast(f16x8, ah);
-                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
-                        A8, __builtin_bit_cast(f16x8, bl), acc[m], 0, 0, 0);
-                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
-                        A8, __builtin_bit_cast(f16x8, bh), acc[m], 0, 0, 0);
-                } else if constexpr (P == P_BF16) {
-                    bf16x8 A8 = __builtin_bit_cast(bf16x8, ah);
-                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                        A8, __builtin_bit_cast(bf16x8, bl), acc[m], 0, 0, 0);
-                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                        A8, __builtin_bit_cast(bf16x8, bh), acc[m], 0, 0, 0);
-                } else {  // P_BF16X3
-                    const uint4 al = *(const uint4 *)(Arow[m] + 2 * Dp + ks * 64);
-                    bf16x8 AH = __builtin_bit_cast(bf16x8, ah);
-                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                        AH, __builtin_bit_cast(bf16x8, bl), acc[m], 0, 0, 0);
-                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                        __builtin_bit_cast(bf16x8, al), __builtin_bit_cast(bf16x8, bh), acc[m],
-                        0, 0, 0);
-                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                        AH, __builtin_bit_cast(bf16x8, bh), acc[m], 0, 0, 0);
+        for (int u = 0; u < PD; ++u)
+#pragma unroll
+            for (int n = 0; n < NTW; ++n)
+                if (ok[n] && u < KS) {
+                    bh[u][n] = Bh[n][u * 64];
+                    bl[u][n] = Bl[n][u * 64];
+                }
+        for (int ks0 = 0; ks0 < KS; ks0 += PD) {
+#pragma unroll
+            for (int u = 0; u < PD; ++u) {
+                const int ks = ks0 + u;
+                if (ks >= KS) break;
+                u32x4 ah[MSW], al[MSW];
+#pragma unroll
+                for (int m = 0; m < MSW; ++m) {
+                    ah[m] = *(const u32x4 *)(Arow[m] + ks * 64);
+                    if constexpr (P == P_BF16X3) al[m] = *(const u32x4 *)(Arow[m] + 2 * Dp + ks * 64);
+                }
+#pragma unroll
+                for (int n = 0; n < NTW; ++n) {
+                    if (!ok[n]) continue;
+                    const u32x4 BH = bh[u][n], BL = bl[u][n];
+#pragma unroll
+                    for (int m = 0; m < MSW; ++m) {
+                        if constexpr (P == P_F16) {
+                            const f16x8 A8 = __builtin_bit_cast(f16x8, ah[m]);
+                            acc[n][m] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                                A8, __builtin_bit_cast(f16x8, BL), acc[n][m], 0, 0, 0);
+                            acc[n][m] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                                A8, __builtin_bit_cast(f16x8, BH), acc[n][m], 0, 0, 0);
+                        } else if constexpr (P == P_BF16) {
+                            const bf16x8 A8 = __builtin_bit_cast(bf16x8, ah[m]);
+                            acc[n][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                A8, __builtin_bit_cast(bf16x8, BL), acc[n][m], 0, 0, 0);
+                            acc[n][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                A8, __builtin_bit_cast(bf16x8, BH), acc[n][m], 0, 0, 0);
+                        } else {  // P_BF16X3
+                            const bf16x8 AH = __builtin_bit_cast(bf16x8, ah[m]);
+                            acc[n][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                AH, __builtin_bit_cast(bf16x8, BL), acc[n][m], 0, 0, 0);
+                            acc[n][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                __builtin_bit_cast(bf16x8, al[m]), __builtin_bit_cast(bf16x8, BH),
+                                acc[n][m], 0, 0, 0);
+                            acc[n][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                AH, __builtin_bit_cast(bf16x8, BH), acc[n][m], 0, 0, 0);
+                        }
+                    }
+                    if (ks + PD < KS) {
+                        bh[u][n] = Bh[n][(ks + PD) * 64];
+                        bl[u][n] = Bl[n][(ks + PD) * 64];
+                    }
                 }
             }
-            bh = bhn;
-            bl = bln;
         }
     }
 }
 
-template <int P, int BM, int WM>
-__global__ __launch_bounds__(kThreads) void pass_kernel(PassArgs A) {
-    typedef typename PT<P>::CT CT;
-    typedef typename PT<P>::CT2 CT2;
-    constexpr int MS = BM / 16;
-    constexpr int MSW = (MS / WM) > 0 ? MS / WM : 1;
-    constexpr int TPR = kThreads / BM;            // threads per row in the row-wise phases
-    constexpr int NPF = 16;                        // prefetch registers (16 B each) per thread
-
-    if ((A.flags & PF_CHECK_STOP) && *A.stopped) return;
-
-    extern __shared__ __align__(16) uint8_t smem[];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const PassLds LY = pass_lds(P, BM, A.K, A.Dp, A.Wp);
-    uint8_t *Vs = smem;
-    CT *Cs = (CT *)(smem + LY.off_c);
-    CT2 *Us = (CT2 *)(smem + LY.off_u);
-    CT *rowf = (CT *)(smem + LY.off_f);
-
-    const int64_t nrows_all = A.row_end - A.row_begin;
-    const int64_t ntiles = (nrows_all + BM - 1) / BM;
-    const int NT = A.Wp / 16;
-    const int WN = 8 / WM;
-    const int wn = wave % WN, wm = wave / WN;
-
-    // Accumulators (FP64 across tiles).
-    double2 accS[kMaxDPerThread];
-    double accW[2];
-    double acc_lse = 0.0, acc_wc = 0.0, acc_rows = 0.0;
+// Accumulators a workgroup carries across its tiles (FP64): S for DPT complex entries per thread,
+// W_t for two window columns per thread, and the per-row sums of log-sum-exp, w*C and rows.
+template <int DPT>
+struct PassAcc {
+    double2 S[DPT];
+    double W[2];
+    double lse, wc, rows;
+    __device__ __forceinline__ void init() {
 #pragma unroll
-    for (int c = 0; c < kMaxDPerThread; ++c) accS[c] = make_double2(0.0, 0.0);
-    accW[0] = accW[1] = 0.0;
+        for (int c = 0; c < DPT; ++c) S[c] = make_double2(0.0, 0.0);
+        W[0] = W[1] = 0.0;
+        lse = wc = rows = 0.0;
+    }
+};
 
-    const float tsc = (P == P_F64 || P == P_F32) ? 1.0f : *A.tscale;
-    const bool accm = (A.flags & PF_ACC_M) != 0;
-
-    // Register prefetch of the next tile: the tile is a contiguous byte range in HBM.
+// Register-staged copy of one row tile (a contiguous byte range of the stored observations) into
+// the LDS tile with padded rows.  issue() starts the loads; store() writes them to LDS.
+template <int NPF>
+struct TileLoader {
     u32x4 pf[NPF];
-    auto issue_load = [&](int64_t tile) {
+    __device__ __forceinline__ void issue(const PassArgs &A, int64_t tile, int BM) {
+        const int tid = threadIdx.x;
         const int64_t r0 = A.row_begin + tile * BM;
         const int64_t rows = (A.row_end - r0) < BM ? (A.row_end - r0) : BM;
         const int64_t nbytes = rows * A.rowbytes;
@@ -481,35 +513,366 @@ __global__ __launch_bounds__(kThreads) void pass_kernel(PassArgs A) {
             const int64_t ch = (int64_t)c * kThreads + tid;
             pf[c] = (ch * 16 < nbytes) ? src[ch] : (u32x4){0u, 0u, 0u, 0u};
         }
-    };
-    auto store_tile = [&]() {
-        const int64_t tbytes = (int64_t)BM * A.rowbytes;
+    }
+    __device__ __forceinline__ void store(uint8_t *Vs, int RS, int BM, int64_t rowbytes) {
+        const int tid = threadIdx.x;
+        const int64_t tbytes = (int64_t)BM * rowbytes;
 #pragma unroll
         for (int c = 0; c < NPF; ++c) {
             const int64_t ch = (int64_t)c * kThreads + tid;
             if (ch * 16 < tbytes) {
-                const int64_t byte = ch * 16;
-                const int r = (int)(byte / A.rowbytes);
-                const int off = (int)(byte - (int64_t)r * A.rowbytes);
-                *(u32x4 *)(Vs + r * LY.RS + off) = pf[c];
+                const int byte = (int)(ch * 16);
+                const int r = byte / (int)rowbytes;
+                const int off = byte - r * (int)rowbytes;
+                *(u32x4 *)(Vs + r * RS + off) = pf[c];
             }
         }
-    };
+    }
+};
+
+// U (BM x 2K, as complex [BM][K]) = w (BM x Wp, the posterior tile in LDS) . [Re E | Im E]
+// (Wp x 2K) on FP32 matrix cores (16x16x4), each row scaled by rowu; wave w computes the 16-column
+// tiles w, w + 8, ... of U for all rows.  The B fragments stream from L2 through a 4-deep ring.
+template <int BM>
+__device__ __forceinline__ void u_mfma(const float *Cs, int CSW, const float *E2, int Wp, int K,
+                                       const float *rowu, float2 *Us) {
+    constexpr int MS = BM / 16, RING = 4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, rl = lane & 15;
+    const int NTU = (2 * K + 15) / 16, KG = Wp / 4;
+    for (int nt = wave; nt < NTU; nt += kThreads / 64) {
+        f32x4 acc[MS];
+#pragma unroll
+        for (int m = 0; m < MS; ++m) acc[m] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        const int col = nt * 16 + rl;
+        const bool cok = col < 2 * K;
+        const float *eb = E2 + (int64_t)g * 2 * K + (cok ? col : 0);
+        float bq[RING];
+#pragma unroll
+        for (int u = 0; u < RING; ++u) bq[u] = (cok && u < KG) ? eb[(int64_t)u * 8 * K] : 0.f;
+        for (int k0 = 0; k0 < KG; k0 += RING) {
+#pragma unroll
+            for (int u = 0; u < RING; ++u) {
+                const int kk = k0 + u;
+                if (kk >= KG) break;
+                const float b = bq[u];
+                if (cok && kk + RING < KG) bq[u] = eb[(int64_t)(kk + RING) * 8 * K];
+#pragma unroll
+                for (int m = 0; m < MS; ++m) {
+                    const float a = Cs[(m * 16 + rl) * CSW + kk * 4 + g];
+                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[m], 0, 0, 0);
+                }
+            }
+        }
+        if (cok) {
+#pragma unroll
+            for (int m = 0; m < MS; ++m)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row = m * 16 + 4 * g + q;
+                    const float v = acc[m][q] * rowu[row];
+                    if (col < K)
+                        Us[row * K + col].x = v;
+                    else
+                        Us[row * K + col - K].y = v;
+                }
+        }
+    }
+}
+
+// The same product with this wave's B fragments already in registers (one U column tile per
+// wave: ucol = 16 wave + lane % 16; KG = Wp / 4 k-steps).
+template <int BM, int KG>
+__device__ __forceinline__ void u_mfma_reg(const float *Cs, int CSW, const float (&ereg)[KG],
+                                           int K, const float *rowu, float2 *Us, bool uact,
+                                           int ucol) {
+    constexpr int MS = BM / 16;
+    if (!uact) return;
+    const int lane = threadIdx.x & 63, g = lane >> 4, rl = lane & 15;
+    f32x4 acc[MS];
+#pragma unroll
+    for (int m = 0; m < MS; ++m) acc[m] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < KG; ++kk)
+#pragma unroll
+        for (int m = 0; m < MS; ++m) {
+            const float a = Cs[(m * 16 + rl) * CSW + kk * 4 + g];
+            acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, ereg[kk], acc[m], 0, 0, 0);
+        }
+    if (ucol < 2 * K) {
+#pragma unroll
+        for (int m = 0; m < MS; ++m)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = m * 16 + 4 * g + q;
+                const float v = acc[m][q] * rowu[row];
+                if (ucol < K)
+                    Us[row * K + ucol].x = v;
+                else
+                    Us[row * K + ucol - K].y = v;
+            }
+    }
+}
+
+// a4 + a5 for one tile whose log-weights l' = coef C + log rho are in Cs (BM x CSW) and whose
+// observation rows are in Vs: per-row log-sum-exp and posteriors, then (with PF_ACC_M) the W_t
+// column sums, U = w E and the M-step accumulation S_d += sum_j U_{j,kbar_d} v_jd.
+// KG > 0: the U B-fragments of this wave are in registers (ereg); KG == 0: they stream from L2.
+template <int P, int BM, int DPT, int KG>
+__device__ __forceinline__ void tile_post(const PassArgs &A, const PassLds &LY, const uint8_t *Vs,
+                                          typename PT<P>::CT *Cs, typename PT<P>::CT2 *Us,
+                                          const float *rowu, const float *lr32, int64_t r0,
+                                          int rows, PassAcc<DPT> &acc,
+                                          const float (&ereg)[KG > 0 ? KG : 1], bool uact,
+                                          int ucol) {
+    typedef typename PT<P>::CT CT;
+    typedef typename PT<P>::CT2 CT2;
+    constexpr int TPR = kThreads / BM;            // threads per row in the row-wise phases
+    const int tid = threadIdx.x;
+    {
+        const int r = tid / TPR, sub = tid % TPR;
+        const bool valid = r < rows;
+        CT *crow = Cs + r * LY.CSW;
+        CT lse;
+        if (A.flags & PF_LOAD_LSE) {
+            lse = valid ? (CT)A.lse[r0 + r] : (CT)0;
+        } else {
+            CT m = -INFINITY;
+            for (int i = sub; i < A.W; i += TPR) m = fmax(m, crow[i]);
+            m = group_max(m, TPR);
+            CT s = 0;
+            for (int i = sub; i < A.W; i += TPR) s += exp(crow[i] - m);
+            s = group_sum(s, TPR);
+            lse = m + log(s);
+        }
+        CT wc = 0;
+        CT b1 = -INFINITY, b2 = -INFINITY;
+        int i1 = 0x7fffffff;
+        const bool query = (A.flags & PF_QUERY) != 0;
+        const int64_t qrow = r0 + r - A.row_begin;
+        for (int i = sub; i < A.Wp; i += TPR) {
+            const CT l = crow[i];
+            CT w = 0;
+            if (i < A.W && valid) {
+                w = exp(l - lse);
+                if (w > (CT)0) {
+                    const CT lr = (P == P_F64) ? (CT)A.logrho64[i] : (CT)lr32[i];
+                    wc += w * (l - lr);
+                }
+                if (query) {
+                    if (A.post) A.post[qrow * A.W + i] = (float)w;
+                    if (l > b1) {
+                        b2 = b1;
+                        b1 = l;
+                        i1 = i;
+                    } else if (l > b2) {
+                        b2 = l;
+                    }
+                }
+            }
+            crow[i] = valid ? w : (CT)0;
+        }
+        wc = group_sum(wc, TPR);
+        if (query) {
+            for (int o = TPR >> 1; o > 0; o >>= 1) {
+                const CT ob1 = __shfl_xor(b1, o, TPR), ob2 = __shfl_xor(b2, o, TPR);
+                const int oi1 = __shfl_xor(i1, o, TPR);
+                if (ob1 > b1 || (ob1 == b1 && oi1 < i1)) {
+                    b2 = fmax(b1, ob2);
+                    b1 = ob1;
+                    i1 = oi1;
+                } else {
+                    b2 = fmax(b2, ob1);
+                }
+            }
+            if (sub == 0 && valid) {
+                if (A.argmax) A.argmax[qrow] = i1;
+                if (A.margin) {
+                    const CT w1 = exp(b1 - lse), w2 = (A.W > 1) ? exp(b2 - lse) : (CT)0;
+                    A.margin[qrow] = (float)(w1 - w2);
+                }
+            }
+        }
+        if (sub == 0 && valid) {
+            acc.lse += (double)lse;
+            acc.wc += (double)wc / A.coef;            // sum_i w_ji C_ji
+            acc.rows += 1.0;
+            if (A.flags & PF_STORE_LSE) A.lse[r0 + r] = (double)lse;
+        }
+    }
+    if (!(A.flags & PF_ACC_M)) return;
+    __syncthreads();
+
+    // W_t column sums
+    for (int c = 0; c < 2; ++c) {
+        const int i = tid + c * kThreads;
+        if (i < A.Wp) {
+            CT s = 0;
+            for (int j = 0; j < rows; ++j) s += Cs[j * LY.CSW + i];
+            acc.W[c] += (double)s;
+        }
+    }
+    // U_jk = sum_i w_ji exp(+i k theta_i), scaled back to the rows' storage scale
+    if constexpr (P == P_F64) {
+        for (int p = tid; p < rows * A.K; p += kThreads) {
+            const int j = p / A.K, k = p - j * A.K;
+            const double *wr = Cs + j * LY.CSW;
+            double ur = 0, ui = 0;
+            for (int i = 0; i < A.W; ++i) {
+                const double2 e = A.E64[i * A.K + k];
+                ur = fma(wr[i], e.x, ur);
+                ui = fma(wr[i], e.y, ui);
+            }
+            Us[p] = make_double2(ur, ui);
+        }
+    } else if constexpr (KG > 0) {
+        u_mfma_reg<BM, KG>(Cs, LY.CSW, ereg, A.K, rowu, Us, uact, ucol);
+    } else {
+        u_mfma<BM>(Cs, LY.CSW, A.E2, A.Wp, A.K, rowu, Us);
+    }
+    __syncthreads();
+    // M-step: S_d += sum_j U_{j, kbar_d} v_jd (complex product, no conjugate)
+#pragma unroll
+    for (int c = 0; c < DPT; ++c) {
+        const int d = tid + c * kThreads;
+        if (d < A.D) {
+            const int k = d / A.Q;
+            CT sr = 0, si = 0;
+            for (int j = 0; j < rows; ++j) {
+                const CT2 v = load_v<P>(Vs + j * LY.RS, d, A.Dp);
+                const CT2 u = Us[j * A.K + k];
+                sr += u.x * v.x - u.y * v.y;
+                si += u.x * v.y + u.y * v.x;
+            }
+            acc.S[c].x += (double)sr;
+            acc.S[c].y += (double)si;
+        }
+    }
+}
+
+// Per-workgroup partials: S (2D), W (Wp), sum lse', sum w*C, rows, 0.
+template <int DPT>
+__device__ __forceinline__ void write_partials(const PassArgs &A, PassAcc<DPT> &acc,
+                                               uint8_t *smem) {
+    const int tid = threadIdx.x;
+    double *Pp = A.partials + (int64_t)blockIdx.x * A.ncols;
+    if (A.flags & PF_ACC_M) {
+#pragma unroll
+        for (int c = 0; c < DPT; ++c) {
+            const int d = tid + c * kThreads;
+            if (d < A.D) {
+                Pp[2 * d] = acc.S[c].x;
+                Pp[2 * d + 1] = acc.S[c].y;
+            }
+        }
+        for (int c = 0; c < 2; ++c) {
+            const int i = tid + c * kThreads;
+            if (i < A.Wp) Pp[2 * A.D + i] = acc.W[c];
+        }
+    } else {
+        for (int i = tid; i < 2 * A.D + A.Wp; i += kThreads) Pp[i] = 0.0;
+    }
+    __syncthreads();
+    double *sh = (double *)smem;
+    const double s_lse = block_sum_d(acc.lse, sh, kThreads);
+    const double s_wc = block_sum_d(acc.wc, sh, kThreads);
+    const double s_rows = block_sum_d(acc.rows, sh, kThreads);
+    if (tid == 0) {
+        Pp[2 * A.D + A.Wp] = s_lse;
+        Pp[2 * A.D + A.Wp + 1] = s_wc;
+        Pp[2 * A.D + A.Wp + 2] = s_rows;
+        Pp[2 * A.D + A.Wp + 3] = 0.0;
+    }
+}
+
+// Asynchronous copy of one row tile into an LDS tile buffer with the direct global-to-LDS load
+// (16 bytes per lane; a wave's 64 lanes fill 1 KB of LDS in lane order).  Rows are whole 1 KB
+// chunks (rowbytes is a multiple of 1024 here); wave w copies chunks w, w + 8, ...  Completion
+// is awaited with s_waitcnt before the barrier that precedes the first read of the buffer.
+__device__ __forceinline__ void dma_issue_tile(const PassArgs &A, int64_t tile, int BM,
+                                              uint8_t *buf, int RS) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t r0 = A.row_begin + tile * BM;
+    const int rows = (int)((A.row_end - r0) < BM ? (A.row_end - r0) : BM);
+    const int cpr = (int)(A.rowbytes >> 10);
+    const int nch = rows * cpr;
+    for (int c = wave; c < nch; c += kThreads / 64) {
+        const int r = c / cpr, k = c - r * cpr;
+        const uint8_t *src = A.V + (r0 + r) * A.rowbytes + k * 1024 + lane * 16;
+        __builtin_amdgcn_global_load_lds(
+            (const void *)src, (__attribute__((address_space(3))) void *)(buf + r * RS + k * 1024),
+            16, 0, 0);
+    }
+}
+
+// General E(+M) pass: the template is streamed from L2 in B-fragment order; the 8 waves split the
+// window's 16-column tiles (WN of them) and the tile's 16-row blocks (WM of them).  LD = 1: the
+// row tile is double-buffered in LDS by direct global-to-LDS copies (rows of whole KiB); LD = 0:
+// it is staged through registers.
+template <int P, int BM, int WM, int LD>
+__global__ __launch_bounds__(kThreads) void pass_kernel(PassArgs A) {
+    typedef typename PT<P>::CT CT;
+    typedef typename PT<P>::CT2 CT2;
+    constexpr int MS = BM / 16;
+    constexpr int MSW = (MS / WM) > 0 ? MS / WM : 1;
+    // column tiles per GEMM pass and template prefetch depth (k-steps); the register-staged
+    // variants keep 64 VGPRs of tile prefetch and so use the lighter setting
+    constexpr int NTW = (WM == 1 && LD) ? ((MSW >= 2 || P != P_F32) ? 2 : 3) : 1;
+    constexpr int PD = (LD && P == P_F32) ? 4 : 2;
+
+    if ((A.flags & PF_CHECK_STOP) && *A.stopped) return;
+
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const PassLds LY = pass_lds(P, BM, A.K, A.Dp, A.Wp, LD ? 2 : 1);
+    CT *Cs = (CT *)(smem + LY.off_c);
+    CT2 *Us = (CT2 *)(smem + LY.off_u);
+    CT *rowf = (CT *)(smem + LY.off_f);
+    float *rowu = (float *)(smem + LY.off_f + BM * sizeof(CT));
+    float *lrs = (float *)(smem + LY.off_lr);
+    for (int i = tid; i < A.Wp; i += kThreads) lrs[i] = A.logrho32[i];
+
+    const int64_t ntiles = (A.row_end - A.row_begin + BM - 1) / BM;
+    const int NT = A.Wp / 16;
+    const int WN = 8 / WM;
+    const int wn = wave % WN, wm = wave / WN;
+
+    PassAcc<kMaxDPerThread> acc;
+    acc.init();
+    const float tsc = (P == P_F64 || P == P_F32) ? 1.0f : *A.tscale;
+    TileLoader<LD ? 1 : kRegTileChunks> ld;
 
     int64_t tile = blockIdx.x;
-    if (tile < ntiles) issue_load(tile);
-    for (; tile < ntiles; tile += gridDim.x) {
+    int buf = 0;
+    if (tile < ntiles) {
+        if constexpr (LD) dma_issue_tile(A, tile, BM, smem, LY.RS);
+        else ld.issue(A, tile, BM);
+    }
+    for (; tile < ntiles; tile += gridDim.x, buf ^= 1) {
         const int64_t r0 = A.row_begin + tile * BM;
         const int rows = (int)((A.row_end - r0) < BM ? (A.row_end - r0) : BM);
-        __syncthreads();                                   // previous tile fully consumed
-        store_tile();
+        uint8_t *Vs = smem + ((LD && buf) ? LY.off_v1 : 0);
+        if constexpr (LD) {
+            __builtin_amdgcn_s_waitcnt(0);                  // this tile's copy has landed
+            __syncthreads();
+            if (tile + gridDim.x < ntiles)
+                dma_issue_tile(A, tile + gridDim.x, BM, smem + (buf ? 0 : LY.off_v1), LY.RS);
+        } else {
+            __syncthreads();                                // previous tile fully consumed
+            ld.store(Vs, LY.RS, BM, A.rowbytes);
+        }
         for (int j = tid; j < BM; j += kThreads) {
             CT f = (CT)A.coef;
-            if (P != P_F64 && A.rowscale && j < rows) f *= (CT)A.rowscale[r0 + j] * (CT)tsc;
+            float u = 1.0f;
+            if (P != P_F64 && A.rowscale && j < rows) {
+                u = A.rowscale[r0 + j];
+                f *= (CT)u * (CT)tsc;
+            }
             rowf[j] = f;
+            rowu[j] = u;
         }
         __syncthreads();
-        if (tile + gridDim.x < ntiles) issue_load(tile + gridDim.x);
+        if constexpr (!LD)
+            if (tile + gridDim.x < ntiles) ld.issue(A, tile + gridDim.x, BM);
 
         // ---- a3: correlations C and log-weights l' = coef * C + log rho  -> Cs
         if constexpr (P == P_F64) {
@@ -523,221 +886,432 @@ __global__ __launch_bounds__(kThreads) void pass_kernel(PassArgs A) {
             }
         } else {
             if (wm < WM) {
-                for (int nt = wn; nt < NT; nt += WN) {
-                    f32x4 acc[MSW];
-                    gemm_ntile<P, MSW, WM>(acc, Vs, LY.RS, wm, lane, nt, A.Dp, A.Thi, A.Tlo);
-                    const int col = nt * 16 + (lane & 15);
-                    const float lr = A.logrho32[col];
+                for (int nt0 = wn; nt0 < NT; nt0 += WN * NTW) {
+                    f32x4 c4[NTW][MSW];
+                    gemm_ntiles<P, MSW, WM, NTW, PD>(c4, Vs, LY.RS, wm, lane, nt0, WN, NT, A.Dp,
+                                                     A.Thi, A.Tlo);
 #pragma unroll
-                    for (int m = 0; m < MSW; ++m) {
-                        const int rb = (wm + m * WM) * 16 + 4 * (lane >> 4);
+                    for (int n = 0; n < NTW; ++n) {
+                        const int nt = nt0 + n * WN;
+                        if (nt >= NT) continue;
+                        const int col = nt * 16 + (lane & 15);
+                        const float lr = lrs[col];
 #pragma unroll
-                        for (int q = 0; q < 4; ++q)
-                            Cs[(rb + q) * LY.CSW + col] = acc[m][q] * rowf[rb + q] + lr;
-                    }
-                }
-            }
-        }
-        __syncthreads();
-
-        // ---- a4: per-row log-sum-exp and posteriors (TPR threads per row)
-        {
-            const int r = tid / TPR, sub = tid % TPR;
-            const bool valid = r < rows;
-            CT *crow = Cs + r * LY.CSW;
-            CT lse;
-            if (A.flags & PF_LOAD_LSE) {
-                lse = valid ? (CT)A.lse[r0 + r] : (CT)0;
-            } else {
-                CT m = -INFINITY;
-                for (int i = sub; i < A.W; i += TPR) m = fmax(m, crow[i]);
-                m = group_max(m, TPR);
-                CT s = 0;
-                for (int i = sub; i < A.W; i += TPR) s += exp(crow[i] - m);
-                s = group_sum(s, TPR);
-                lse = m + log(s);
-            }
-            CT wc = 0;
-            CT b1 = -INFINITY, b2 = -INFINITY;
-            int i1 = 0x7fffffff;
-            const bool query = (A.flags & PF_QUERY) != 0;
-            const int64_t qrow = r0 + r - A.row_begin;
-            for (int i = sub; i < A.Wp; i += TPR) {
-                const CT l = crow[i];
-                CT w = 0;
-                if (i < A.W && valid) {
-                    w = exp(l - lse);
-                    if (w > (CT)0) {
-                        const CT lr = (P == P_F64) ? (CT)A.logrho64[i] : (CT)A.logrho32[i];
-                        wc += w * (l - lr);
-                    }
-                    if (query) {
-                        if (A.post) A.post[qrow * A.W + i] = (float)w;
-                        if (l > b1) {
-                            b2 = b1;
-                            b1 = l;
-                            i1 = i;
-                        } else if (l > b2) {
-                            b2 = l;
+                        for (int m = 0; m < MSW; ++m) {
+                            const int rb = (wm + m * WM) * 16 + 4 * (lane >> 4);
+#pragma unroll
+                            for (int q = 0; q < 4; ++q)
+                                Cs[(rb + q) * LY.CSW + col] = c4[n][m][q] * rowf[rb + q] + lr;
                         }
                     }
                 }
-                crow[i] = valid ? w : (CT)0;
-            }
-            wc = group_sum(wc, TPR);
-            if (query) {
-                for (int o = TPR >> 1; o > 0; o >>= 1) {
-                    const CT ob1 = __shfl_xor(b1, o, TPR), ob2 = __shfl_xor(b2, o, TPR);
-                    const int oi1 = __shfl_xor(i1, o, TPR);
-                    if (ob1 > b1 || (ob1 == b1 && oi1 < i1)) {
-                        b2 = fmax(b1, ob2);
-                        b1 = ob1;
-                        i1 = oi1;
-                    } else {
-                        b2 = fmax(b2, ob1);
-                    }
-                }
-                if (sub == 0 && valid) {
-                    if (A.argmax) A.argmax[qrow] = i1;
-                    if (A.margin) {
-                        const CT w1 = exp(b1 - lse), w2 = (A.W > 1) ? exp(b2 - lse) : (CT)0;
-                        A.margin[qrow] = (float)(w1 - w2);
-                    }
-                }
-            }
-            if (sub == 0 && valid) {
-                acc_lse += (double)lse;
-                acc_wc += (double)wc / A.coef;            // sum_i w_ji C_ji
-                acc_rows += 1.0;
-                if (A.flags & PF_STORE_LSE) A.lse[r0 + r] = (double)lse;
             }
         }
-        if (!accm) continue;
         __syncthreads();
-
-        // ---- a5: W_t column sums, U = w E (scaled back to the observations' storage scale)
-        for (int c = 0; c < 2; ++c) {
-            const int i = tid + c * kThreads;
-            if (i < A.Wp) {
-                CT s = 0;
-                for (int j = 0; j < rows; ++j) s += Cs[j * LY.CSW + i];
-                accW[c] += (double)s;
-            }
-        }
-        // U_jk = sum_i w_ji exp(+i k theta_i) for kUR rows at a time, then the M-step over them:
-        // S_d += sum_j U_{j, kbar_d} v_jd (complex product, no conjugate).
-        for (int j0 = 0; j0 < rows; j0 += kUR) {
-            const int nr = (rows - j0) < kUR ? (rows - j0) : kUR;
-            for (int p = tid; p < nr * A.K; p += kThreads) {
-                const int jj = p / A.K, k = p - jj * A.K;
-                const CT *wr = Cs + (j0 + jj) * LY.CSW;
-                CT ur = 0, ui = 0;
-                for (int i = 0; i < A.W; ++i) {
-                    const CT w = wr[i];
-                    if constexpr (P == P_F64) {
-                        const double2 e = A.E64[i * A.K + k];
-                        ur = fma(w, e.x, ur);
-                        ui = fma(w, e.y, ui);
-                    } else {
-                        const float2 e = A.E32[i * A.K + k];
-                        ur = fmaf(w, e.x, ur);
-                        ui = fmaf(w, e.y, ui);
-                    }
-                }
-                if (P != P_F64 && A.rowscale) {
-                    const CT f = (CT)A.rowscale[r0 + j0 + jj];
-                    ur *= f;
-                    ui *= f;
-                }
-                CT2 u;
-                u.x = ur;
-                u.y = ui;
-                Us[p] = u;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int c = 0; c < kMaxDPerThread; ++c) {
-                const int d = tid + c * kThreads;
-                if (d < A.D) {
-                    const int k = d / A.Q;
-                    CT sr = 0, si = 0;
-                    for (int jj = 0; jj < nr; ++jj) {
-                        const CT2 v = load_v<P>(Vs + (j0 + jj) * LY.RS, d, A.Dp);
-                        const CT2 u = Us[jj * A.K + k];
-                        sr += u.x * v.x - u.y * v.y;
-                        si += u.x * v.y + u.y * v.x;
-                    }
-                    accS[c].x += (double)sr;
-                    accS[c].y += (double)si;
-                }
-            }
-            __syncthreads();
-        }
+        const float nore[1] = {0.f};
+        tile_post<P, BM, kMaxDPerThread, 0>(A, LY, Vs, Cs, Us, rowu, lrs, r0, rows, acc, nore,
+                                            false, 0);
     }
-
-    if (A.partials == nullptr) return;
-    // ---- per-workgroup partials: S (2D), W (Wp), sum lse', sum w*C, rows
-    double *Pp = A.partials + (int64_t)blockIdx.x * A.ncols;
-    if (accm) {
-#pragma unroll
-        for (int c = 0; c < kMaxDPerThread; ++c) {
-            const int d = tid + c * kThreads;
-            if (d < A.D) {
-                Pp[2 * d] = accS[c].x;
-                Pp[2 * d + 1] = accS[c].y;
-            }
-        }
-        for (int c = 0; c < 2; ++c) {
-            const int i = tid + c * kThreads;
-            if (i < A.Wp) Pp[2 * A.D + i] = accW[c];
-        }
-    } else {
-        for (int i = tid; i < 2 * A.D + A.Wp; i += kThreads) Pp[i] = 0.0;
-    }
-    __syncthreads();
-    double *sh = (double *)smem;
-    const double s_lse = block_sum_d(acc_lse, sh, kThreads);
-    const double s_wc = block_sum_d(acc_wc, sh, kThreads);
-    const double s_rows = block_sum_d(acc_rows, sh, kThreads);
-    if (tid == 0) {
-        Pp[2 * A.D + A.Wp] = s_lse;
-        Pp[2 * A.D + A.Wp + 1] = s_wc;
-        Pp[2 * A.D + A.Wp + 2] = s_rows;
-        Pp[2 * A.D + A.Wp + 3] = 0.0;
-    }
+    if (A.partials) write_partials(A, acc, smem);
 }
 
 // ------------------------------------------------------------------------------------------
-// a6: FP64 finalize (one workgroup of 256).
+// K-split E(+M) pass for windows whose whole template fits in the register file: wave w holds
+// the template rows of its K-slice (KSS k-steps of 32 reals) for all NT column tiles, loaded once
+// per launch; per tile every wave contracts its K-slice of the tile's rows against it, and the
+// eight partial correlations are summed in a fixed order through LDS (waves 4-7 into 0-3, then
+// ((s0 + s1) + s2) + s3), so the result does not depend on scheduling.
 
-__global__ __launch_bounds__(256) void finalize_kernel(FinArgs F) {
+struct KsLds {
+    int RS, CSW;
+    int off_v1, off_red, off_c, off_u, off_f, off_lr, total;
+};
+__host__ __device__ inline KsLds ks_lds(int prec, int BM, int NT, int K, int Dp, int Wp) {
+    KsLds l;
+    l.RS = (int)row_bytes(prec, Dp) + 16;
+    l.CSW = Wp + 1;
+    l.off_v1 = align_up(BM * l.RS, 16);                     // second tile buffer
+    l.off_red = align_up(2 * BM * l.RS, 16);
+    l.off_c = align_up(l.off_red + 4 * (BM / 16) * NT * 64 * 16, 16);
+    l.off_u = align_up(l.off_c + BM * l.CSW * 4, 16);
+    l.off_f = align_up(l.off_u + BM * K * 8, 16);
+    l.off_lr = align_up(l.off_f + 2 * BM * 4, 16);
+    l.total = l.off_lr + Wp * 4 + 16;
+    return l;
+}
+
+template <int P>
+__host__ __device__ constexpr int bytes_per_real() {
+    return P == P_BF16X3 ? 4 : (P == P_F32 ? 4 : 2);
+}
+
+// Wave-wide reductions with DPP butterflies inside each 16-lane row (xor 1, xor 2, half-mirror,
+// mirror), then the four row results combined in a fixed order through readlane.  Every lane
+// must be active.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float rl_f(float v, int lane) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+__device__ __forceinline__ float wave_max_f(float v) {
+    v = fmaxf(v, dpp_f<0xB1>(v));     // quad_perm [1,0,3,2]
+    v = fmaxf(v, dpp_f<0x4E>(v));     // quad_perm [2,3,0,1]
+    v = fmaxf(v, dpp_f<0x141>(v));    // row_half_mirror
+    v = fmaxf(v, dpp_f<0x140>(v));    // row_mirror
+    return fmaxf(fmaxf(rl_f(v, 0), rl_f(v, 16)), fmaxf(rl_f(v, 32), rl_f(v, 48)));
+}
+__device__ __forceinline__ float wave_sum_f(float v) {
+    v += dpp_f<0xB1>(v);
+    v += dpp_f<0x4E>(v);
+    v += dpp_f<0x141>(v);
+    v += dpp_f<0x140>(v);
+    return (rl_f(v, 0) + rl_f(v, 16)) + (rl_f(v, 32) + rl_f(v, 48));
+}
+
+// a4 + a5 of the K-split pass without posterior queries: wave w owns the rows w, w + 8, ... of
+// the tile with one window column per lane (Wp <= 64).  It sums the eight K-slices of its rows,
+// forms the log-weights, their log-sum-exp and the posteriors in registers, adds the posteriors
+// to its per-lane W_t accumulator and leaves them in Cs; then U = w E on matrix cores and the
+// M-step over the tile's rows.
+template <int P, int BM, int NT, int DPT, int KG>
+__device__ __forceinline__ void ks_post(const PassArgs &A, const KsLds &LY, const uint8_t *Vs,
+                                        const f32x4 *red, float *Cs, float2 *Us,
+                                        const float *rowf, const float *rowu, const float *lrs,
+                                        int64_t r0, int rows, PassAcc<DPT> &acc, double &accWl,
+                                        const float (&ereg)[KG], bool uact, int ucol) {
+    constexpr int MS = BM / 16;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int col = lane, nt = lane >> 4;
+    const bool cval = col < A.W;
+    const float lr = col < A.Wp ? lrs[col] : -INFINITY;
+    float wsum = 0.f;
+#pragma unroll
+    for (int h = 0; h < BM / 8; ++h) {
+        const int r = wave + 8 * h;
+        const bool rval = r < rows;
+        const int m = r >> 4, rr = r & 15;
+        const int ln = (rr >> 2) * 16 + (col & 15), q = rr & 3;
+        float l = -INFINITY;
+        if (cval && rval) {
+            float v = red[((0 * MS + m) * NT + nt) * 64 + ln][q];
+            v += red[((1 * MS + m) * NT + nt) * 64 + ln][q];
+            v += red[((2 * MS + m) * NT + nt) * 64 + ln][q];
+            v += red[((3 * MS + m) * NT + nt) * 64 + ln][q];
+            l = v * rowf[r] + lr;
+        }
+        float lse;
+        if (A.flags & PF_LOAD_LSE) {
+            lse = rval ? (float)A.lse[r0 + r] : 0.f;
+        } else {
+            const float mx = wave_max_f(l);
+            const float s = wave_sum_f((cval && rval) ? __expf(l - mx) : 0.f);
+            lse = mx + __logf(s);
+        }
+        const float w = (cval && rval) ? __expf(l - lse) : 0.f;
+        const float wc = wave_sum_f(w > 0.f ? w * (l - lr) : 0.f);
+        if (col < A.Wp) Cs[r * LY.CSW + col] = w;
+        wsum += w;
+        if (lane == 0 && rval) {
+            acc.lse += (double)lse;
+            acc.wc += (double)wc / A.coef;
+            acc.rows += 1.0;
+            if (A.flags & PF_STORE_LSE) A.lse[r0 + r] = (double)lse;
+        }
+    }
+    accWl += (double)wsum;
+    if (!(A.flags & PF_ACC_M)) return;
+    __syncthreads();
+    u_mfma_reg<BM, KG>(Cs, LY.CSW, ereg, A.K, rowu, Us, uact, ucol);
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < DPT; ++c) {
+        const int d = tid + c * kThreads;
+        if (d < A.D) {
+            const int k = d / A.Q;
+            float sr = 0.f, si = 0.f;
+#pragma unroll
+            for (int j = 0; j < BM; ++j) {
+                if (j < rows) {
+                    const float2 v = load_v<P>(Vs + j * LY.RS, d, A.Dp);
+                    const float2 u = Us[j * A.K + k];
+                    sr += u.x * v.x - u.y * v.y;
+                    si += u.x * v.y + u.y * v.x;
+                }
+            }
+            acc.S[c].x += (double)sr;
+            acc.S[c].y += (double)si;
+        }
+    }
+}
+
+template <int P, int BM, int NT, int KSS, int QRY>
+__global__ __launch_bounds__(kThreads) void pass_ks_kernel(PassArgs A) {
+    constexpr int MS = BM / 16;
+    constexpr int DPT = (KSS * 128 + kThreads - 1) / kThreads;
+    constexpr int KG = NT * 4;                              // k-steps of the U product (Wp / 4)
+    static_assert(P == P_BF16X3 || P == P_F16 || P == P_BF16, "16-bit MFMA paths only");
+    typedef typename std::conditional<P == P_F16, _Float16, __bf16>::type H;
+
+    if ((A.flags & PF_CHECK_STOP) && *A.stopped) return;
+
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, rl = lane & 15;
+    const KsLds LY = ks_lds(P, BM, NT, A.K, A.Dp, A.Wp);
+    f32x4 *red = (f32x4 *)(smem + LY.off_red);
+    float *Cs = (float *)(smem + LY.off_c);
+    float2 *Us = (float2 *)(smem + LY.off_u);
+    float *rowf = (float *)(smem + LY.off_f);
+    float *rowu = rowf + BM;
+    float *lrs = (float *)(smem + LY.off_lr);
+    PassLds PL;                                             // the view tile_post expects
+    PL.RS = LY.RS;
+    PL.CSW = LY.CSW;
+    const int D = A.D, K = A.K;
+
+    // log rho into LDS; template scale from max |Re a|, |Im a| (a power of two, see the
+    // storage-scaling note above)
+    for (int i = tid; i < A.Wp; i += kThreads) lrs[i] = A.logrho32[i];
+    double amax = 0.0;
+    for (int r = tid; r < 2 * D; r += kThreads) amax = fmax(amax, fabs(A.a[r]));
+    amax = -block_min_d(-amax, (double *)(smem + LY.off_red), kThreads);
+    float sc = 1.0f, tsc = 1.0f;
+    if (amax > 0.0) {
+        const int e = ilogb(amax);
+        sc = ldexpf(1.0f, scale_target(P) - e);
+        tsc = ldexpf(1.0f, e - scale_target(P));
+    }
+
+    // this wave's template K-slice for all column tiles, built from a_t in registers:
+    // T[r][i] = (Re, Im)(a_d conj(exp(+i k_d theta_i))) * sc, d = r / 2, split into hi + lo
+    u32x4 treg[KSS][NT][2];
+#pragma unroll
+    for (int ks = 0; ks < KSS; ++ks) {
+        const int d0 = ((wave * KSS + ks) * 32 + 8 * g) >> 1;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const float *Ei = A.E2 + (int64_t)(nt * 16 + rl) * 2 * K;
+            H hv[8], lv[8];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int d = d0 + e;
+                float tre = 0.f, tim = 0.f;
+                if (d < D) {
+                    const int k = d / A.Q;
+                    const float are = (float)A.a[2 * d], aim = (float)A.a[2 * d + 1];
+                    const float er = Ei[k], ei = Ei[K + k];
+                    tre = (are * er + aim * ei) * sc;
+                    tim = (aim * er - are * ei) * sc;
+                }
+                hv[2 * e] = (H)tre;
+                hv[2 * e + 1] = (H)tim;
+                lv[2 * e] = (H)(tre - (float)hv[2 * e]);
+                lv[2 * e + 1] = (H)(tim - (float)hv[2 * e + 1]);
+            }
+            treg[ks][nt][0] = __builtin_bit_cast(u32x4, hv);
+            treg[ks][nt][1] = __builtin_bit_cast(u32x4, lv);
+        }
+    }
+    // B fragments of U = w [Re E | Im E] for this wave's 16-column tile of U
+    const int ucol = wave * 16 + rl;
+    const bool uact = wave * 16 < 2 * K, uok = ucol < 2 * K;
+    float ereg[KG];
+#pragma unroll
+    for (int kk = 0; kk < KG; ++kk)
+        ereg[kk] = uok ? A.E2[(int64_t)(kk * 4 + g) * 2 * K + ucol] : 0.f;
+
+    const int64_t ntiles = (A.row_end - A.row_begin + BM - 1) / BM;
+    PassAcc<DPT> acc;
+    acc.init();
+    double accWl = 0.0;                                     // this lane's W_t column (fast path)
+    constexpr bool query = QRY != 0;                        // posterior queries: generic path
+
+    int64_t tile = blockIdx.x;
+    int buf = 0;
+    float rs_next = 1.0f;                                   // next tile's row scale (tid < BM)
+    if (tile < ntiles) {
+        dma_issue_tile(A, tile, BM, smem, LY.RS);
+        const int64_t r0 = A.row_begin + tile * BM;
+        if (tid < BM && r0 + tid < A.row_end && A.rowscale) rs_next = A.rowscale[r0 + tid];
+    }
+    for (; tile < ntiles; tile += gridDim.x, buf ^= 1) {
+        const int64_t r0 = A.row_begin + tile * BM;
+        const int rows = (int)((A.row_end - r0) < BM ? (A.row_end - r0) : BM);
+        uint8_t *Vs = smem + (buf ? LY.off_v1 : 0);
+        const float rs = rs_next;
+        __builtin_amdgcn_s_waitcnt(0);                      // this tile's copy has landed
+        __syncthreads();                                    // ... for every wave; old tile done
+        if (tile + gridDim.x < ntiles) {
+            const int64_t rn = A.row_begin + (tile + gridDim.x) * BM;
+            dma_issue_tile(A, tile + gridDim.x, BM, smem + (buf ? 0 : LY.off_v1), LY.RS);
+            if (tid < BM && rn + tid < A.row_end && A.rowscale) rs_next = A.rowscale[rn + tid];
+        }
+        if (tid < BM) {
+            const float u = tid < rows ? rs : 1.0f;
+            rowf[tid] = (float)A.coef * u * tsc;
+            rowu[tid] = u;
+        }
+
+        // ---- a3: partial correlations over this wave's K-slice
+        f32x4 c4[MS][NT];
+#pragma unroll
+        for (int m = 0; m < MS; ++m)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) c4[m][nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KSS; ++ks) {
+            const int kstep = wave * KSS + ks;
+#pragma unroll
+            for (int m = 0; m < MS; ++m) {
+                const uint8_t *arow = Vs + (m * 16 + rl) * LY.RS + kstep * 64 + g * 16;
+                const u32x4 ah = *(const u32x4 *)arow;
+                if constexpr (P == P_BF16X3) {
+                    const u32x4 al = *(const u32x4 *)(arow + 2 * A.Dp);
+                    const bf16x8 AH = __builtin_bit_cast(bf16x8, ah);
+                    const bf16x8 AL = __builtin_bit_cast(bf16x8, al);
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) {
+                        c4[m][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            AH, __builtin_bit_cast(bf16x8, treg[ks][nt][1]), c4[m][nt], 0, 0, 0);
+                        c4[m][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            AL, __builtin_bit_cast(bf16x8, treg[ks][nt][0]), c4[m][nt], 0, 0, 0);
+                        c4[m][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            AH, __builtin_bit_cast(bf16x8, treg[ks][nt][0]), c4[m][nt], 0, 0, 0);
+                    }
+                } else if constexpr (P == P_F16) {
+                    const f16x8 AH = __builtin_bit_cast(f16x8, ah);
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) {
+                        c4[m][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                            AH, __builtin_bit_cast(f16x8, treg[ks][nt][1]), c4[m][nt], 0, 0, 0);
+                        c4[m][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                            AH, __builtin_bit_cast(f16x8, treg[ks][nt][0]), c4[m][nt], 0, 0, 0);
+                    }
+                } else {
+                    const bf16x8 AH = __builtin_bit_cast(bf16x8, ah);
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) {
+                        c4[m][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            AH, __builtin_bit_cast(bf16x8, treg[ks][nt][1]), c4[m][nt], 0, 0, 0);
+                        c4[m][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            AH, __builtin_bit_cast(bf16x8, treg[ks][nt][0]), c4[m][nt], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        // ---- fixed-order sum of the eight K-slices: slot k = slice k + slice k+4
+        if (wave >= 4) {
+#pragma unroll
+            for (int m = 0; m < MS; ++m)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    red[(((wave - 4) * MS + m) * NT + nt) * 64 + lane] = c4[m][nt];
+        }
+        __syncthreads();
+        if (wave < 4) {
+#pragma unroll
+            for (int m = 0; m < MS; ++m)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    f32x4 *slot = &red[((wave * MS + m) * NT + nt) * 64 + lane];
+                    *slot = c4[m][nt] + *slot;
+                }
+        }
+        __syncthreads();
+        if constexpr (!query) {
+            ks_post<P, BM, NT, DPT, KG>(A, LY, Vs, red, Cs, Us, rowf, rowu, lrs, r0, rows, acc,
+                                         accWl, ereg, uact, ucol);
+            continue;
+        }
+        for (int o = tid; o < BM * A.Wp; o += kThreads) {
+            const int row = o / A.Wp, col = o - row * A.Wp;
+            const int m = row >> 4, rr = row & 15, nt = col >> 4;
+            const int ln = (rr >> 2) * 16 + (col & 15), q = rr & 3;
+            float v = red[((0 * MS + m) * NT + nt) * 64 + ln][q];
+            v += red[((1 * MS + m) * NT + nt) * 64 + ln][q];
+            v += red[((2 * MS + m) * NT + nt) * 64 + ln][q];
+            v += red[((3 * MS + m) * NT + nt) * 64 + ln][q];
+            Cs[row * LY.CSW + col] = v * rowf[row] + lrs[col];
+        }
+        __syncthreads();
+        if constexpr (query)
+            tile_post<P, BM, DPT, KG>(A, PL, Vs, Cs, Us, rowu, lrs, r0, rows, acc, ereg, uact,
+                                      ucol);
+    }
+    if constexpr (!query) {
+        // the per-lane W_t columns of the eight waves, summed in wave order
+        __syncthreads();
+        double *wsh = (double *)(smem + LY.off_red);
+        wsh[wave * 64 + lane] = accWl;
+        __syncthreads();
+        acc.W[0] = acc.W[1] = 0.0;
+        if (tid < 64) {
+            double t = 0.0;
+            for (int k = 0; k < kThreads / 64; ++k) t += wsh[k * 64 + tid];
+            acc.W[0] = t;
+        }
+    }
+    if (A.partials) write_partials(A, acc, smem);
+}
+
+// ------------------------------------------------------------------------------------------
+// a6: FP64 finalize (one workgroup of kFinThreads).
+
+constexpr int kFinThreads = 512;
+constexpr int kFinPhaseLds = 2048;                 // phase table staged in LDS up to this L
+
+// Deterministic block sums of NV doubles per thread in one pass (fixed tree order).
+template <int NV>
+__device__ __forceinline__ void block_sum_multi(double (&v)[NV], double *sh) {
+    const int t = threadIdx.x;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sh[k * kFinThreads + t] = v[k];
+    __syncthreads();
+    for (int s = kFinThreads >> 1; s > 0; s >>= 1) {
+        if (t < s)
+#pragma unroll
+            for (int k = 0; k < NV; ++k) sh[k * kFinThreads + t] += sh[k * kFinThreads + t + s];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = sh[k * kFinThreads];
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kFinThreads) void finalize_kernel(FinArgs F) {
     if (F.mode == FIN_EM && *F.stopped) return;
-    __shared__ double sh[256];
+    __shared__ double sh[5 * kFinThreads];
     __shared__ double2 anew[kMaxD];
     __shared__ double2 ck[kMaxK];
+    __shared__ double2 ph[kFinPhaseLds];
     const int t = threadIdx.x;
-    const int D = F.D, W = F.W;
+    const int D = F.D, W = F.W, K = F.K, L = F.L;
     const double N = (double)F.N;
     const double *S = F.red;
     const double *Wt = F.red + 2 * D;
     const double s_lse = F.red[2 * D + F.Wp];
     const double s_wc = F.red[2 * D + F.Wp + 1];
 
-    double an2 = 0.0;
-    for (int r = t; r < 2 * D; r += 256) an2 += F.a_in[r] * F.a_in[r];
-    an2 = block_sum_d(an2, sh, 256);
-    const double ll = s_lse - (F.sum_vn2 + N * an2) / F.sigma2 -
-                      N * (double)D * log(M_PI * F.sigma2);
-
-    if (F.mode == FIN_LL) {
-        if (t == 0) F.out[0] = ll;
-        return;
-    }
-    if (F.mode == FIN_GRAD) {
+    if (F.mode != FIN_EM) {
+        double v[1] = {0.0};
+        for (int r = t; r < 2 * D; r += kFinThreads) v[0] += F.a_in[r] * F.a_in[r];
+        block_sum_multi<1>(v, sh);
+        const double an2 = v[0];
+        const double ll = s_lse - (F.sum_vn2 + N * an2) / F.sigma2 -
+                          N * (double)D * log(M_PI * F.sigma2);
+        if (F.mode == FIN_LL) {
+            if (t == 0) F.out[0] = ll;
+            return;
+        }
         const double c = F.g * 2.0 / F.sigma2;
-        for (int r = t; r < 2 * D; r += 256) F.grad_a[r] = c * (S[r] - N * F.a_in[r]);
+        for (int r = t; r < 2 * D; r += kFinThreads) F.grad_a[r] = c * (S[r] - N * F.a_in[r]);
         if (F.grad_eta)
-            for (int i = t; i < W; i += 256) F.grad_eta[i] = F.g * (Wt[i] - N * F.rho_in[i]);
+            for (int i = t; i < W; i += kFinThreads)
+                F.grad_eta[i] = F.g * (Wt[i] - N * F.rho_in[i]);
         if (t == 0) {
             const double swr = F.sum_vn2 + N * an2 - 2.0 * s_wc;
             F.out[0] = ll;
@@ -746,27 +1320,34 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs F) {
         return;
     }
 
-    // FIN_EM
-    double jprior = 0.0;
-    for (int i = t; i < W; i += 256)
-        if (F.rho_bar[i] > 0.0 && F.gamma != 0.0) jprior += F.gamma * F.rho_bar[i] * log(F.rho_in[i]);
-    for (int d = t; d < D; d += 256)
-        if (F.gai) jprior -= F.gai[d] * (F.a_in[2 * d] * F.a_in[2 * d] + F.a_in[2 * d + 1] * F.a_in[2 * d + 1]);
-    jprior = block_sum_d(jprior, sh, 256);
-
-    double nn2 = 0.0, dl2 = 0.0;
-    for (int d = t; d < D; d += 256) {
-        const double den = N + (F.gai ? F.sigma2 * F.gai[d] : 0.0);
+    // FIN_EM.  Pass 1: ||a_t||^2, MAP prior terms, a_{t+1}, ||a_{t+1}||^2, ||a_{t+1} - a_t||^2,
+    // the rho normaliser; phase table into LDS.
+    const bool ph_lds = L <= kFinPhaseLds;
+    if (ph_lds)
+        for (int m = t; m < L; m += kFinThreads) ph[m] = F.phase[m];
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int d = t; d < D; d += kFinThreads) {
+        const double ar = F.a_in[2 * d], ai = F.a_in[2 * d + 1];
+        const double g = F.gai ? F.gai[d] : 0.0;
+        const double den = N + F.sigma2 * g;
         const double2 an = make_double2(S[2 * d] / den, S[2 * d + 1] / den);
         anew[d] = an;
-        nn2 += an.x * an.x + an.y * an.y;
-        const double ex = an.x - F.a_in[2 * d], ey = an.y - F.a_in[2 * d + 1];
-        dl2 += ex * ex + ey * ey;
+        v[0] += ar * ar + ai * ai;
+        v[1] -= g * (ar * ar + ai * ai);
+        v[2] += an.x * an.x + an.y * an.y;
+        v[3] += (an.x - ar) * (an.x - ar) + (an.y - ai) * (an.y - ai);
     }
-    nn2 = block_sum_d(nn2, sh, 256);
-    dl2 = block_sum_d(dl2, sh, 256);
+    for (int i = t; i < W; i += kFinThreads) {
+        if (F.gamma != 0.0 && F.rho_bar[i] > 0.0) v[1] += F.gamma * F.rho_bar[i] * log(F.rho_in[i]);
+        v[4] += Wt[i] + F.gamma * F.rho_bar[i];
+    }
+    block_sum_multi<5>(v, sh);
+    const double an2 = v[0], jprior = v[1], nn2 = v[2], dl2 = v[3], tot = v[4];
+    const double ll = s_lse - (F.sum_vn2 + N * an2) / F.sigma2 -
+                      N * (double)D * log(M_PI * F.sigma2);
+
     // c_k = sum_q conj(a_new[k,q]) a_t[k,q]
-    for (int k = t; k < F.K; k += 256) {
+    for (int k = t; k < K; k += kFinThreads) {
         double cr = 0.0, ci = 0.0;
         for (int q = 0; q < F.Q; ++q) {
             const int d = k * F.Q + q;
@@ -778,32 +1359,46 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs F) {
         ck[k] = make_double2(cr, ci);
     }
     __syncthreads();
-    // stopping metric min_l ||a_new - exp(-2 pi i kbar l / L) a_t||^2
+    // Pass 2: stopping metric min_l ||a_new - exp(-2 pi i kbar l / L) a_t||^2 and the entropy
+    // of rho_{t+1}
     double best = INFINITY;
-    for (int l = t; l < F.L; l += 256) {
+    for (int l = t; l < L; l += kFinThreads) {
         double re = 0.0;
-        for (int k = 0; k < F.K; ++k) {
-            const double2 ph = F.phase[((int64_t)k * l) % F.L];   // exp(+2 pi i k l / L)
-            re += ck[k].x * ph.x + ck[k].y * ph.y;                 // Re(c_k exp(-2 pi i k l/L))
+        int m = 0;                                          // (k l) mod L, incrementally
+        for (int k = 0; k < K; ++k) {
+            const double2 p = ph_lds ? ph[m] : F.phase[m];   // exp(+2 pi i k l / L)
+            re += ck[k].x * p.x + ck[k].y * p.y;             // Re(c_k exp(-2 pi i k l / L))
+            m += l;
+            if (m >= L) m -= L;
         }
         best = fmin(best, nn2 + an2 - 2.0 * re);
     }
-    best = block_min_d(best, sh, 256);
-
-    // rho update
-    double tot = 0.0;
-    for (int i = t; i < W; i += 256) tot += Wt[i] + F.gamma * F.rho_bar[i];
-    tot = block_sum_d(tot, sh, 256);
     double ent = 0.0;
-    for (int i = t; i < W; i += 256) {
+    for (int i = t; i < W; i += kFinThreads) {
         const double rn = F.update_rho ? (Wt[i] + F.gamma * F.rho_bar[i]) / tot : F.rho_in[i];
         if (rn > 0.0) ent -= rn * log(rn);
     }
-    ent = block_sum_d(ent, sh, 256);
-    __syncthreads();
+    {
+        double w2[2] = {-best, ent};
+        // min via max of negatives, with the same fixed tree as the sums
+        __syncthreads();
+        sh[t] = w2[0];
+        sh[kFinThreads + t] = w2[1];
+        __syncthreads();
+        for (int s = kFinThreads >> 1; s > 0; s >>= 1) {
+            if (t < s) {
+                sh[t] = fmax(sh[t], sh[t + s]);
+                sh[kFinThreads + t] += sh[kFinThreads + t + s];
+            }
+            __syncthreads();
+        }
+        best = -sh[0];
+        ent = sh[kFinThreads];
+        __syncthreads();
+    }
     if (F.update_rho)
-        for (int i = t; i < W; i += 256) F.rho[i] = (Wt[i] + F.gamma * F.rho_bar[i]) / tot;
-    for (int d = t; d < D; d += 256) {
+        for (int i = t; i < W; i += kFinThreads) F.rho[i] = (Wt[i] + F.gamma * F.rho_bar[i]) / tot;
+    for (int d = t; d < D; d += kFinThreads) {
         F.a[2 * d] = anew[d].x;
         F.a[2 * d + 1] = anew[d].y;
     }
@@ -916,7 +1511,7 @@ hipError_t launch_template(const TplArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_finalize(const FinArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kFinThreads), 0, s, a);
     return hipGetLastError();
 }
 
@@ -930,62 +1525,124 @@ hipError_t launch_histogram(const int32_t *err, int64_t n, int L, unsigned long 
     return hipGetLastError();
 }
 
-size_t pass_lds_bytes(int prec, int BM, int D, int K, int Dp, int Wp) {
-    (void)D;
-    return (size_t)pass_lds(prec, BM, K, Dp, Wp).total;
+size_t pass_lds_bytes(int prec, int BM, int K, int Dp, int Wp, int LD) {
+    return (size_t)pass_lds(prec, BM, K, Dp, Wp, LD ? 2 : 1).total;
 }
-
-// Variant table: (precision, rows per tile, waves along rows).
-#define SEM_PASS_VARIANTS(X)                                                                   \
-    X(P_F64, 16, 1) X(P_F64, 32, 1) X(P_F64, 64, 1)                                            \
-    X(P_F32, 16, 1) X(P_F32, 32, 1) X(P_F32, 32, 2) X(P_F32, 64, 1) X(P_F32, 64, 2)             \
-    X(P_F32, 64, 4)                                                                            \
-    X(P_BF16X3, 16, 1) X(P_BF16X3, 32, 1) X(P_BF16X3, 32, 2) X(P_BF16X3, 64, 1)                 \
-    X(P_BF16X3, 64, 2) X(P_BF16X3, 64, 4)                                                      \
-    X(P_F16, 16, 1) X(P_F16, 32, 1) X(P_F16, 32, 2) X(P_F16, 64, 1) X(P_F16, 64, 2)             \
-    X(P_F16, 64, 4)                                                                            \
-    X(P_BF16, 16, 1) X(P_BF16, 32, 1) X(P_BF16, 32, 2) X(P_BF16, 64, 1) X(P_BF16, 64, 2)        \
-    X(P_BF16, 64, 4)
 
 typedef void (*pass_fn)(PassArgs);
 
-static pass_fn find_pass(int prec, int BM, int WM) {
-#define SEM_X(P, B, M)                                                                         \
-    if (prec == P && BM == B && WM == M) return pass_kernel<P, B, M>;
+// General pass variants: (precision, rows per tile, waves along rows, loader).
+#define SEM_PASS_VARIANTS(X)                                                                   \
+    X(P_F64, 8, 1, 0) X(P_F64, 16, 1, 0) X(P_F64, 32, 1, 0) X(P_F64, 16, 1, 1)                 \
+    X(P_F64, 32, 1, 1)                                                                         \
+    X(P_F32, 16, 1, 0) X(P_F32, 32, 1, 0) X(P_F32, 32, 2, 0) X(P_F32, 64, 1, 0)                \
+    X(P_F32, 64, 2, 0) X(P_F32, 64, 4, 0) X(P_F32, 16, 1, 1) X(P_F32, 32, 1, 1)                \
+    X(P_F32, 32, 2, 1)                                                                         \
+    X(P_BF16X3, 16, 1, 0) X(P_BF16X3, 32, 1, 0) X(P_BF16X3, 32, 2, 0) X(P_BF16X3, 64, 1, 0)     \
+    X(P_BF16X3, 64, 2, 0) X(P_BF16X3, 64, 4, 0) X(P_BF16X3, 16, 1, 1)                          \
+    X(P_F16, 16, 1, 0) X(P_F16, 32, 1, 0) X(P_F16, 32, 2, 0) X(P_F16, 64, 1, 0)                \
+    X(P_F16, 64, 2, 0) X(P_F16, 64, 4, 0) X(P_F16, 16, 1, 1) X(P_F16, 32, 1, 1)                \
+    X(P_F16, 32, 2, 1)                                                                         \
+    X(P_BF16, 16, 1, 0) X(P_BF16, 32, 1, 0) X(P_BF16, 32, 2, 0) X(P_BF16, 64, 1, 0)            \
+    X(P_BF16, 64, 2, 0) X(P_BF16, 64, 4, 0) X(P_BF16, 16, 1, 1) X(P_BF16, 32, 1, 1)            \
+    X(P_BF16, 32, 2, 1)
+
+static pass_fn find_pass(int prec, int BM, int WM, int LD) {
+#define SEM_X(P, B, M, D)                                                                      \
+    if (prec == P && BM == B && WM == M && LD == D) return pass_kernel<P, B, M, D>;
     SEM_PASS_VARIANTS(SEM_X)
 #undef SEM_X
     return nullptr;
 }
 
-bool pass_variant_exists(int prec, int BM, int WM) { return find_pass(prec, BM, WM) != nullptr; }
+bool pass_variant_exists(int prec, int BM, int WM, int LD) {
+    return find_pass(prec, BM, WM, LD) != nullptr;
+}
 
-const char *pass_kernel_name(int prec, int BM, int WM) {
+static const char *kPrecName[] = {"f64", "f32", "bf16x3", "f16", "bf16"};
+
+const char *pass_kernel_name(int prec, int BM, int WM, int LD) {
     static char buf[64];
-    static const char *pn[] = {"f64", "f32", "bf16x3", "f16", "bf16"};
-    snprintf(buf, sizeof buf, "pass_kernel<%s,BM=%d,WM=%d>", pn[prec], BM, WM);
+    snprintf(buf, sizeof buf, "pass_kernel<%s,BM=%d,WM=%d,%s>", kPrecName[prec], BM, WM,
+             LD ? "dma" : "reg");
     return buf;
 }
 
-hipError_t pass_set_lds_limit(int prec, int BM, int WM, size_t lds) {
-    pass_fn f = find_pass(prec, BM, WM);
+hipError_t pass_setup(int prec, int BM, int WM, int LD, size_t lds, int *blocks_per_cu) {
+    pass_fn f = find_pass(prec, BM, WM, LD);
     if (!f) return hipErrorInvalidValue;
-    return hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds);
-}
-
-hipError_t pass_occupancy(int prec, int BM, int WM, size_t lds, int *blocks_per_cu) {
-    pass_fn f = find_pass(prec, BM, WM);
-    if (!f) return hipErrorInvalidValue;
+    hipError_t e = hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) (void)hipGetLastError();
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void *)f, kThreads,
                                                         lds);
 }
 
-hipError_t launch_pass(int prec, int BM, int WM, const PassArgs &a, int grid, size_t lds,
+hipError_t launch_pass(int prec, int BM, int WM, int LD, const PassArgs &a, int grid, size_t lds,
                        hipStream_t s) {
-    pass_fn f = find_pass(prec, BM, WM);
+    pass_fn f = find_pass(prec, BM, WM, LD);
     if (!f) return hipErrorInvalidValue;
     hipLaunchKernelGGL(f, dim3(grid), dim3(kThreads), lds, s, a);
     return hipGetLastError();
+}
+
+// K-split variants: (precision, rows per tile, column tiles, k-steps per wave); Dp = 256 KSS.
+#define SEM_KS_VARIANTS(X)                                                                     \
+    X(P_BF16X3, 16, 4, 4) X(P_BF16X3, 16, 3, 4) X(P_F16, 16, 4, 4) X(P_F16, 16, 3, 4)           \
+    X(P_BF16, 16, 4, 4) X(P_BF16, 16, 3, 4)
+
+static pass_fn find_ks(int prec, int BM, int NT, int KSS, int QRY = 0) {
+#define SEM_X(P, B, N, S)                                                                      \
+    if (prec == P && BM == B && NT == N && KSS == S)                                           \
+        return QRY ? pass_ks_kernel<P, B, N, S, 1> : pass_ks_kernel<P, B, N, S, 0>;
+    SEM_KS_VARIANTS(SEM_X)
+#undef SEM_X
+    return nullptr;
+}
+
+bool ks_plan(int prec, int Dp, int Wp, int K, int *BM, int *NT, int *KSS) {
+    const int nt = Wp / 16, kss = Dp / 256;
+    if (Dp % 256 != 0 || 2 * K > 16 * (kThreads / 64)) return false;   // one U tile per wave
+    for (int bm : {32, 16})
+        if (find_ks(prec, bm, nt, kss)) {
+            *BM = bm;
+            *NT = nt;
+            *KSS = kss;
+            return true;
+        }
+    return false;
+}
+
+size_t ks_lds_bytes(int prec, int BM, int NT, int K, int Dp, int Wp) {
+    return (size_t)ks_lds(prec, BM, NT, K, Dp, Wp).total;
+}
+
+hipError_t launch_pass_ks(int prec, int BM, int NT, int KSS, const PassArgs &a, int grid,
+                          size_t lds, hipStream_t s) {
+    pass_fn f = find_ks(prec, BM, NT, KSS, (a.flags & PF_QUERY) ? 1 : 0);
+    if (!f) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(f, dim3(grid), dim3(kThreads), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t pass_ks_setup(int prec, int BM, int NT, int KSS, size_t lds, int *blocks_per_cu) {
+    pass_fn f = find_ks(prec, BM, NT, KSS);
+    if (!f) return hipErrorInvalidValue;
+    hipError_t e = hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) (void)hipGetLastError();
+    e = hipFuncSetAttribute((const void *)find_ks(prec, BM, NT, KSS, 1),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) (void)hipGetLastError();
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void *)f, kThreads,
+                                                        lds);
+}
+
+const char *pass_ks_name(int prec, int BM, int NT, int KSS) {
+    static char buf[64];
+    snprintf(buf, sizeof buf, "pass_ks_kernel<%s,BM=%d,NT=%d,KSS=%d>", kPrecName[prec], BM, NT,
+             KSS);
+    return buf;
 }
 
 }  // namespace sem
