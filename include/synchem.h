@@ -60,6 +60,8 @@ typedef enum { EM_FP64 = 0, EM_FP32 = 1, EM_BF16X3 = 2, EM_FP16 = 3, EM_BF16 = 4
 #define EM_FLAG_KEEP_LSE  (1ull << 0)   /* em_step also stores the per-observation log-likelihood */
 #define EM_FLAG_TIMING    (1ull << 1)   /* time every E+M pass with HIP events (em_pass_time)     */
 #define EM_FLAG_GENERAL_PASS (1ull << 2) /* never use the register-resident-template pass variant */
+#define EM_FLAG_WIDE_PASS (1ull << 3)   /* EM_FP16 / EM_BF16: always use the wide-row pass variant
+                                           (chosen by itself when a row tile does not fit in LDS) */
 
 typedef struct {
     int64_t n_obs;          /* N >= 1                                                        */

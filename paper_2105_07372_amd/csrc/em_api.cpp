@@ -40,6 +40,8 @@ struct em_ctx {
     int LD = 0;           // general pass: 1 = tile double-buffered by direct global-to-LDS copies
     bool ks = false;      // K-split pass (template resident in registers)
     int ksNT = 0, ksKSS = 0;
+    bool wide = false;    // wide-row pass (rows streamed through an LDS ring, 128-row tiles)
+    int wNTW = 0, wUR = 0;
     int64_t rowbytes = 0;
     size_t lds = 0;
     hipStream_t stream = nullptr;
@@ -125,6 +127,21 @@ int pow2_floor(int x) {
 // Choose rows per tile and the wave split of the pass for this problem.
 em_status plan(em_ctx *c, size_t lds_max) {
     c->ks = false;
+    c->wide = false;
+    const bool one_plane = c->prec == P_F16 || c->prec == P_BF16;
+    if (one_plane && (c->flags & EM_FLAG_WIDE_PASS)) {
+        int NTW = 0, UR = 0;
+        if (wide_plan(c->prec, c->Wp, c->K, lds_max, &NTW, &UR)) {
+            c->wide = true;
+            c->BM = kWideBM;
+            c->wNTW = NTW;
+            c->wUR = UR;
+            c->WM = 0;
+            c->lds = wide_lds_bytes(c->K, c->Wp, UR);
+            return EM_OK;
+        }
+        return fail(c, EM_EUNSUPPORTED, "no wide-row pass variant for this window and K");
+    }
     if (c->prec != P_F64 && c->prec != P_F32 && !(c->flags & EM_FLAG_GENERAL_PASS)) {
         int BM = 0, NT = 0, KSS = 0;
         if (ks_plan(c->prec, c->Dp, c->Wp, c->K, &BM, &NT, &KSS)) {
@@ -160,6 +177,19 @@ em_status plan(em_ctx *c, size_t lds_max) {
             break;
         }
     }
+    if (!c->BM && one_plane) {
+        // rows too long for a tile in LDS: stream them through the wide-row pass
+        int NTW = 0, UR = 0;
+        if (wide_plan(c->prec, c->Wp, c->K, lds_max, &NTW, &UR)) {
+            c->wide = true;
+            c->BM = kWideBM;
+            c->wNTW = NTW;
+            c->wUR = UR;
+            c->WM = 0;
+            c->lds = wide_lds_bytes(c->K, c->Wp, UR);
+            return EM_OK;
+        }
+    }
     if (!c->BM)
         return fail(c, EM_EUNSUPPORTED,
                     "observation rows too wide for this build (row of " +
@@ -190,7 +220,8 @@ em_status check_params(const em_params *p) {
         return fail(nullptr, EM_EINVAL, "update_rho must be 0 or 1");
     if (p->precision < EM_FP64 || p->precision > EM_BF16)
         return fail(nullptr, EM_EINVAL, "unknown precision");
-    if (p->flags & ~(uint64_t)(EM_FLAG_KEEP_LSE | EM_FLAG_TIMING | EM_FLAG_GENERAL_PASS))
+    if (p->flags & ~(uint64_t)(EM_FLAG_KEEP_LSE | EM_FLAG_TIMING | EM_FLAG_GENERAL_PASS |
+                               EM_FLAG_WIDE_PASS))
         return fail(nullptr, EM_EINVAL, "unknown flag bits");
     if (p->window_lo < -(1 << 30) || p->window_lo > (1 << 30))
         return fail(nullptr, EM_EINVAL, "window_lo out of range");
@@ -275,6 +306,8 @@ em_status run_pass(em_ctx *c, int flags, int64_t r0, int64_t r1, const double *a
     if (ev) HIPCHK(c, hipEventRecord(c->ev[c->ev_used], c->stream));
     if (c->ks)
         HIPCHK(c, launch_pass_ks(c->prec, c->BM, c->ksNT, c->ksKSS, A, grid, c->lds, c->stream));
+    else if (c->wide)
+        HIPCHK(c, launch_pass_wide(c->prec, c->wNTW, c->wUR, A, grid, c->lds, c->stream));
     else
         HIPCHK(c, launch_pass(c->prec, c->BM, c->WM, c->LD, A, grid, c->lds, c->stream));
     if (ev) {
@@ -420,6 +453,11 @@ em_status em_init(em_ctx **out, const em_params *p, const void *obs_dev, const d
     if (c->ks) {
         if (pass_ks_setup(c->prec, c->BM, c->ksNT, c->ksKSS, c->lds, &occ) != hipSuccess ||
             occ < 1) {
+            (void)hipGetLastError();
+            occ = 1;
+        }
+    } else if (c->wide) {
+        if (pass_wide_setup(c->prec, c->wNTW, c->wUR, c->lds, &occ) != hipSuccess || occ < 1) {
             (void)hipGetLastError();
             occ = 1;
         }
@@ -811,8 +849,9 @@ em_status em_get_info(const em_ctx *c, em_info *info) {
     info->bytes_per_row = c->rowbytes;
     info->lds_bytes = (int64_t)c->lds;
     std::snprintf(info->kernel, sizeof info->kernel, "%s",
-                  c->ks ? pass_ks_name(c->prec, c->BM, c->ksNT, c->ksKSS)
-                        : pass_kernel_name(c->prec, c->BM, c->WM, c->LD));
+                  c->ks     ? pass_ks_name(c->prec, c->BM, c->ksNT, c->ksKSS)
+                  : c->wide ? pass_wide_name(c->prec, c->wNTW, c->wUR)
+                            : pass_kernel_name(c->prec, c->BM, c->WM, c->LD));
     return EM_OK;
 }
 

@@ -24,6 +24,7 @@ constexpr int kMaxD = kMaxDPerThread * kThreads;
 constexpr int kMaxWp = 1024;         // padded window <= 2 * kThreads
 constexpr int kMaxK = 512;
 constexpr int kStatsCap = 1024;
+constexpr int kWideBM = 128;         // rows per tile of the wide-row pass
 constexpr int kRegTileChunks = 8;    // register-staged tiles: <= 8 x 16 B per thread (64 KiB)
 
 // Bytes of one stored observation row (all planes), Dp reals wide.
@@ -124,5 +125,11 @@ hipError_t launch_pass_ks(int prec, int BM, int NT, int KSS, const PassArgs &a, 
                           size_t lds, hipStream_t s);
 hipError_t pass_ks_setup(int prec, int BM, int NT, int KSS, size_t lds, int *blocks_per_cu);
 const char *pass_ks_name(int prec, int BM, int NT, int KSS);
+bool wide_plan(int prec, int Wp, int K, size_t lds_max, int *NTW, int *UR);
+size_t wide_lds_bytes(int K, int Wp, int UR);
+hipError_t launch_pass_wide(int prec, int NTW, int UR, const PassArgs &a, int grid, size_t lds,
+                            hipStream_t s);
+hipError_t pass_wide_setup(int prec, int NTW, int UR, size_t lds, int *blocks_per_cu);
+const char *pass_wide_name(int prec, int NTW, int UR);
 
 }  // namespace sem

@@ -613,25 +613,19 @@ __device__ __forceinline__ void u_mfma_reg(const float *Cs, int CSW, const float
     }
 }
 
-// a4 + a5 for one tile whose log-weights l' = coef C + log rho are in Cs (BM x CSW) and whose
-// observation rows are in Vs: per-row log-sum-exp and posteriors, then (with PF_ACC_M) the W_t
-// column sums, U = w E and the M-step accumulation S_d += sum_j U_{j,kbar_d} v_jd.
-// KG > 0: the U B-fragments of this wave are in registers (ereg); KG == 0: they stream from L2.
-template <int P, int BM, int DPT, int KG>
-__device__ __forceinline__ void tile_post(const PassArgs &A, const PassLds &LY, const uint8_t *Vs,
-                                          typename PT<P>::CT *Cs, typename PT<P>::CT2 *Us,
-                                          const float *rowu, const float *lr32, int64_t r0,
-                                          int rows, PassAcc<DPT> &acc,
-                                          const float (&ereg)[KG > 0 ? KG : 1], bool uact,
-                                          int ucol) {
+// The row-wise part of tile_post: log-sum-exp, posteriors (left in Cs, zero on padding rows and
+// columns), the per-row sums and the posterior queries.
+template <int P, int BM, int DPT>
+__device__ __forceinline__ void tile_rows(const PassArgs &A, int CSW, typename PT<P>::CT *Cs,
+                                          const float *lr32, int64_t r0, int rows,
+                                          PassAcc<DPT> &acc) {
     typedef typename PT<P>::CT CT;
-    typedef typename PT<P>::CT2 CT2;
-    constexpr int TPR = kThreads / BM;            // threads per row in the row-wise phases
+    constexpr int TPR = kThreads / BM;            // threads per row
     const int tid = threadIdx.x;
     {
         const int r = tid / TPR, sub = tid % TPR;
         const bool valid = r < rows;
-        CT *crow = Cs + r * LY.CSW;
+        CT *crow = Cs + r * CSW;
         CT lse;
         if (A.flags & PF_LOAD_LSE) {
             lse = valid ? (CT)A.lse[r0 + r] : (CT)0;
@@ -699,18 +693,43 @@ __device__ __forceinline__ void tile_post(const PassArgs &A, const PassLds &LY, 
             if (A.flags & PF_STORE_LSE) A.lse[r0 + r] = (double)lse;
         }
     }
-    if (!(A.flags & PF_ACC_M)) return;
-    __syncthreads();
+}
 
-    // W_t column sums
+// W_t column sums of the posteriors of one tile (after tile_rows and a barrier).
+template <int P, int DPT>
+__device__ __forceinline__ void tile_wsum(const PassArgs &A, int CSW,
+                                          const typename PT<P>::CT *Cs, int rows,
+                                          PassAcc<DPT> &acc) {
+    typedef typename PT<P>::CT CT;
+    const int tid = threadIdx.x;
     for (int c = 0; c < 2; ++c) {
         const int i = tid + c * kThreads;
         if (i < A.Wp) {
             CT s = 0;
-            for (int j = 0; j < rows; ++j) s += Cs[j * LY.CSW + i];
+            for (int j = 0; j < rows; ++j) s += Cs[j * CSW + i];
             acc.W[c] += (double)s;
         }
     }
+}
+
+// a4 + a5 for one tile whose log-weights l' = coef C + log rho are in Cs (BM x CSW) and whose
+// observation rows are in Vs: per-row log-sum-exp and posteriors, then (with PF_ACC_M) the W_t
+// column sums, U = w E and the M-step accumulation S_d += sum_j U_{j,kbar_d} v_jd.
+// KG > 0: the U B-fragments of this wave are in registers (ereg); KG == 0: they stream from L2.
+template <int P, int BM, int DPT, int KG>
+__device__ __forceinline__ void tile_post(const PassArgs &A, const PassLds &LY, const uint8_t *Vs,
+                                          typename PT<P>::CT *Cs, typename PT<P>::CT2 *Us,
+                                          const float *rowu, const float *lr32, int64_t r0,
+                                          int rows, PassAcc<DPT> &acc,
+                                          const float (&ereg)[KG > 0 ? KG : 1], bool uact,
+                                          int ucol) {
+    typedef typename PT<P>::CT CT;
+    typedef typename PT<P>::CT2 CT2;
+    const int tid = threadIdx.x;
+    tile_rows<P, BM, DPT>(A, LY.CSW, Cs, lr32, r0, rows, acc);
+    if (!(A.flags & PF_ACC_M)) return;
+    __syncthreads();
+    tile_wsum<P, DPT>(A, LY.CSW, Cs, rows, acc);
     // U_jk = sum_i w_ji exp(+i k theta_i), scaled back to the rows' storage scale
     if constexpr (P == P_F64) {
         for (int p = tid; p < rows * A.K; p += kThreads) {
@@ -1258,6 +1277,303 @@ __global__ __launch_bounds__(kThreads) void pass_ks_kernel(PassArgs A) {
 }
 
 // ------------------------------------------------------------------------------------------
+// Wide-row E(+M) pass, for rows too long to double-buffer a tile of them in LDS (D = 2048 in
+// fp16 is 8 KiB per row).  A tile is kWideBM = 128 rows.  The eight waves are 4 window groups x
+// 2 K-halves: wave (iw, kh) accumulates the window tiles iw, iw + 4, .. (NTW of them) for all 8
+// row blocks of the tile over its half of the 2D reals.  The product is formed transposed
+// (template fragments as the A operand, observation fragments as B), so the accumulators come
+// out with one observation row per lane column.  The row tile streams through a ring of
+// kWideSlots LDS slots (kWideKSS k-steps of each half per slot) by direct global-to-LDS copies;
+// template fragments stream from L2 one slot ahead.  Every wave issues the same number of vector
+// memory loads per slot (out-of-range k-steps and window tiles load a valid dummy address), so
+// a fixed s_waitcnt count makes slot s resident while slots s+1, s+2 stay in flight.  The two
+// K-halves are summed through the C tile in LDS (a two-term sum, so the order cannot change
+// it); then the posteriors (tile_rows), W_t, and U = w E and the M-step in chunks of UR rows,
+// the M-step reading the tile's rows again from global memory.
+
+constexpr int kWideSlots = 3;
+constexpr int kWideKSS = 2;
+
+struct WideLds {
+    int CSW, slot_bytes, off_u, off_f, off_lr, off_s, total;
+};
+__host__ __device__ inline WideLds wide_lds(int K, int Wp, int UR) {
+    WideLds l;
+    l.CSW = Wp + 4;                                    // float4 rows, conflict-free columns
+    l.slot_bytes = 2 * kWideKSS * kWideBM * 64;        // [half][k-step][row][64 B]
+    const int ring = kWideSlots * l.slot_bytes;
+    l.off_u = align_up(kWideBM * l.CSW * 4, 16);
+    const int post = l.off_u + UR * K * 8;
+    l.off_f = align_up(ring > post ? ring : post, 16);
+    l.off_lr = l.off_f + 2 * kWideBM * 4;
+    l.off_s = align_up(l.off_lr + Wp * 4, 16);
+    l.total = l.off_s + kMaxD * 16;                    // FP64 M-step sums, kept across tiles
+    return l;
+}
+
+// s_waitcnt with only the vector-memory count constrained (gfx9 encoding), then a compiler
+// barrier so no memory access moves across it.
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+    asm volatile("" ::: "memory");
+}
+
+// Workgroup barrier for LDS hand-offs only: waits for this wave's LDS accesses, not for its
+// vector-memory loads (a __syncthreads() would also drain the copies still in flight).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_s_waitcnt(15 | (7 << 4) | (0 << 8) | (3 << 14));
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+__device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
+                                             0x00020000);
+}
+
+// Slot s of the tile behind rsrc V: k-steps half_base + s KSS + ss of its 128 rows; wave w copies
+// row block w of both halves and both k-steps (4 copies of 1 KiB).  voff = this lane's byte
+// offset (row, clamped to the tile, and 16-byte piece); k-steps past the end copy a valid
+// stand-in that is never used.
+__device__ __forceinline__ void wide_dma(rsrc_t V, uint32_t voff, int s, int KS, int KH0,
+                                         uint8_t *slot) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int ss = 0; ss < kWideKSS; ++ss) {
+            int ks = (h ? KH0 : 0) + s * kWideKSS + ss;
+            ks = ks < KS ? ks : KS - 1;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                V,
+                (__attribute__((address_space(3))) void *)(slot + ((h * kWideKSS + ss) * kWideBM +
+                                                                   16 * wave) * 64),
+                16, voff, (uint32_t)ks * 64u, 0, 0);
+        }
+}
+
+// Template fragments of k-step ks (clamped into [0, ke)) for this wave's window tiles; toff[n]
+// is the byte offset of tile n's fragment column for this lane.
+template <int NTW>
+__device__ __forceinline__ void wide_tload(rsrc_t Th, rsrc_t Tl, const uint32_t (&toff)[NTW],
+                                           int ks, int ke, u32x4 (&th)[NTW], u32x4 (&tl)[NTW]) {
+    int k = ks < ke ? ks : ke - 1;
+    k = k < 0 ? 0 : k;
+    const uint32_t so = (uint32_t)k * 1024u;
+#pragma unroll
+    for (int n = 0; n < NTW; ++n) {
+        th[n] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(Th, toff[n], so, 0));
+        tl[n] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(Tl, toff[n], so, 0));
+    }
+}
+
+template <int P, int NTW, int UR>
+__global__ __launch_bounds__(kThreads) void pass_wide_kernel(PassArgs A) {
+    static_assert(P == P_F16 || P == P_BF16, "one 16-bit observation plane");
+    constexpr int BM = kWideBM, MJ = BM / 16, DPT = kMaxDPerThread;
+    constexpr int NTL = kWideKSS * NTW * 2;            // template loads per wave per slot
+    constexpr int NDL = 2 * kWideKSS;                  // LDS copies per wave per slot
+
+    if ((A.flags & PF_CHECK_STOP) && *A.stopped) return;
+
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform, in an SGPR
+    const int g = lane >> 4, c = lane & 15;
+    const WideLds LY = wide_lds(A.K, A.Wp, UR);
+    float *Cs = (float *)smem;
+    float2 *Us = (float2 *)(smem + LY.off_u);
+    float *rowf = (float *)(smem + LY.off_f);
+    float *rowu = rowf + BM;
+    float *lrs = (float *)(smem + LY.off_lr);
+    double2 *Sacc = (double2 *)(smem + LY.off_s);      // thread t owns entries t, t + 512, ..
+    for (int i = tid; i < A.Wp; i += kThreads) lrs[i] = A.logrho32[i];
+    for (int d = tid; d < kMaxD; d += kThreads) Sacc[d] = make_double2(0.0, 0.0);
+    const float tsc = *A.tscale;
+
+    const int NT = A.Wp / 16, KS = A.Dp / 32;
+    const int KH0 = (KS + 1) / 2;
+    const int NS = (KH0 + kWideKSS - 1) / kWideKSS;
+    const int iw = wave & 3, kh = wave >> 2;
+    const int kb = kh ? KH0 : 0, ke = kh ? KS : KH0;
+    const uint32_t tbytes = (uint32_t)NT * KS * 1024u;
+    const rsrc_t Th = make_rsrc(A.Thi, tbytes), Tl = make_rsrc(A.Tlo, tbytes);
+    uint32_t toff[NTW];
+#pragma unroll
+    for (int n = 0; n < NTW; ++n) {
+        const int nt = iw + 4 * n < NT ? iw + 4 * n : 0;
+        toff[n] = ((uint32_t)nt * KS * 64u + lane) * 16u;
+    }
+
+    PassAcc<DPT> acc;
+    acc.init();
+    const int64_t ntiles = (A.row_end - A.row_begin + BM - 1) / BM;
+    float rs_next = 1.0f;
+    int64_t tile = blockIdx.x;
+    if (tile < ntiles) {
+        const int64_t r0 = A.row_begin + tile * BM;
+        if (tid < BM && r0 + tid < A.row_end && A.rowscale) rs_next = A.rowscale[r0 + tid];
+    }
+    for (; tile < ntiles; tile += gridDim.x) {
+        const int64_t r0 = A.row_begin + tile * BM;
+        const int rows = (int)((A.row_end - r0) < BM ? (A.row_end - r0) : BM);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();                               // the previous tile's post phase is done
+        if (tid < BM) {
+            const float u = tid < rows ? rs_next : 1.0f;
+            rowf[tid] = (float)A.coef * u * tsc;
+            rowu[tid] = u;
+        }
+
+        // ---- a3: this wave's window tiles over its K-half, slot by slot
+        f32x4 ac[NTW][MJ];
+#pragma unroll
+        for (int n = 0; n < NTW; ++n)
+#pragma unroll
+            for (int m = 0; m < MJ; ++m) ac[n][m] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        u32x4 th[kWideKSS][NTW], tl[kWideKSS][NTW];
+        const rsrc_t Vt = make_rsrc(A.V + r0 * A.rowbytes, (uint32_t)(rows * A.rowbytes));
+        uint32_t voff;
+        {
+            const int row = 16 * wave + (lane >> 2);
+            voff = (uint32_t)((row < rows ? row : rows - 1) * A.rowbytes) + (lane & 3) * 16u;
+        }
+        // Every slot step issues the same loads (stand-ins past the end, copied into slots that
+        // are free), so the loop body is the same on every trip and slot s is resident once at
+        // most the last NTL + NDL loads of this wave are outstanding.
+        wide_dma(Vt, voff, 0, KS, KH0, smem);
+        asm volatile("" ::: "memory");                 // keep the steady-state issue order
+#pragma unroll
+        for (int ss = 0; ss < kWideKSS; ++ss)
+            wide_tload<NTW>(Th, Tl, toff, kb + ss, ke, th[ss], tl[ss]);
+        asm volatile("" ::: "memory");
+        wide_dma(Vt, voff, 1, KS, KH0, smem + LY.slot_bytes);
+        for (int s = 0; s < NS; ++s) {
+            wait_vm<NTL + NDL>();
+            lds_barrier();
+            const uint8_t *slot = smem + (s % kWideSlots) * LY.slot_bytes;
+#pragma unroll
+            for (int ss = 0; ss < kWideKSS; ++ss) {
+                const int ks = kb + s * kWideKSS + ss;
+                if (ks < ke) {
+#pragma unroll
+                    for (int m = 0; m < MJ; ++m) {
+                        const u32x4 vf = *(const u32x4 *)(slot + ((kh * kWideKSS + ss) * BM +
+                                                                  16 * m + c) * 64 + g * 16);
+#pragma unroll
+                        for (int n = 0; n < NTW; ++n) {
+                            // (a tile past the window's end multiplies a stand-in fragment;
+                            // its accumulator is never stored)
+                            if constexpr (P == P_F16) {
+                                const f16x8 V8 = __builtin_bit_cast(f16x8, vf);
+                                ac[n][m] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                                    __builtin_bit_cast(f16x8, tl[ss][n]), V8, ac[n][m], 0, 0, 0);
+                                ac[n][m] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                                    __builtin_bit_cast(f16x8, th[ss][n]), V8, ac[n][m], 0, 0, 0);
+                            } else {
+                                const bf16x8 V8 = __builtin_bit_cast(bf16x8, vf);
+                                ac[n][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                    __builtin_bit_cast(bf16x8, tl[ss][n]), V8, ac[n][m], 0, 0, 0);
+                                ac[n][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                    __builtin_bit_cast(bf16x8, th[ss][n]), V8, ac[n][m], 0, 0, 0);
+                            }
+                        }
+                    }
+                }
+                wide_tload<NTW>(Th, Tl, toff, kb + (s + 1) * kWideKSS + ss, ke, th[ss], tl[ss]);
+            }
+            asm volatile("" ::: "memory");
+            wide_dma(Vt, voff, s + 2, KS, KH0, smem + ((s + 2) % kWideSlots) * LY.slot_bytes);
+        }
+
+        // ---- the two K-halves summed into the C tile (which overlays the ring), then
+        // l' = coef C + log rho; next tile's row scale
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (kh == 0) {
+#pragma unroll
+            for (int n = 0; n < NTW; ++n) {
+                const int nt = iw + 4 * n;
+                if (nt >= NT) continue;
+#pragma unroll
+                for (int m = 0; m < MJ; ++m)
+                    *(f32x4 *)(Cs + (16 * m + c) * LY.CSW + 16 * nt + 4 * g) = ac[n][m];
+            }
+        }
+        __syncthreads();
+        if (kh == 1) {
+#pragma unroll
+            for (int n = 0; n < NTW; ++n) {
+                const int nt = iw + 4 * n;
+                if (nt >= NT) continue;
+                const f32x4 lr4 = *(const f32x4 *)(lrs + 16 * nt + 4 * g);
+#pragma unroll
+                for (int m = 0; m < MJ; ++m) {
+                    f32x4 *p = (f32x4 *)(Cs + (16 * m + c) * LY.CSW + 16 * nt + 4 * g);
+                    const float rf = rowf[16 * m + c];
+                    const f32x4 o = *p;
+                    f32x4 l;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) l[q] = (o[q] + ac[n][m][q]) * rf + lr4[q];
+                    *p = l;
+                }
+            }
+        }
+        if (tile + gridDim.x < ntiles) {
+            const int64_t rn = A.row_begin + (tile + gridDim.x) * BM;
+            if (tid < BM && rn + tid < A.row_end && A.rowscale) rs_next = A.rowscale[rn + tid];
+        }
+        __syncthreads();
+
+        // ---- a4 + a5
+        tile_rows<P, BM, DPT>(A, LY.CSW, Cs, lrs, r0, rows, acc);
+        if (!(A.flags & PF_ACC_M)) continue;
+        __syncthreads();
+        tile_wsum<P, DPT>(A, LY.CSW, Cs, rows, acc);
+        for (int rc = 0; rc < rows; rc += UR) {
+            if (rc) __syncthreads();                   // the previous chunk's U is consumed
+            u_mfma<UR>(Cs + rc * LY.CSW, LY.CSW, A.E2, A.Wp, A.K, rowu + rc, Us);
+            __syncthreads();
+            const int nr = rows - rc < UR ? rows - rc : UR;
+            const uint8_t *vb = A.V + (r0 + rc) * A.rowbytes;
+#pragma unroll
+            for (int cc = 0; cc < DPT; ++cc) {
+                const int d = tid + cc * kThreads;
+                if (d >= A.D) continue;
+                const int k = d / A.Q;
+                float sr = 0.f, si = 0.f;
+                for (int j0 = 0; j0 < nr; j0 += 8) {
+                    float2 v[8];
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) {
+                        const int j = j0 + t < nr ? j0 + t : nr - 1;
+                        v[t] = load_v<P>(vb + (int64_t)j * A.rowbytes, d, A.Dp);
+                    }
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) {
+                        if (j0 + t < nr) {
+                            const float2 u = Us[(j0 + t) * A.K + k];
+                            sr += u.x * v[t].x - u.y * v[t].y;
+                            si += u.x * v[t].y + u.y * v[t].x;
+                        }
+                    }
+                }
+                Sacc[d].x += (double)sr;
+                Sacc[d].y += (double)si;
+            }
+        }
+    }
+#pragma unroll
+    for (int cc = 0; cc < DPT; ++cc) acc.S[cc] = Sacc[tid + cc * kThreads];
+    __syncthreads();
+    if (A.partials) write_partials(A, acc, smem);
+}
+
+// ------------------------------------------------------------------------------------------
 // a6: FP64 finalize (one workgroup of kFinThreads).
 
 constexpr int kFinThreads = 512;
@@ -1642,6 +1958,55 @@ const char *pass_ks_name(int prec, int BM, int NT, int KSS) {
     static char buf[64];
     snprintf(buf, sizeof buf, "pass_ks_kernel<%s,BM=%d,NT=%d,KSS=%d>", kPrecName[prec], BM, NT,
              KSS);
+    return buf;
+}
+
+// Wide-row variants: (precision, window tiles per wave group, U chunk rows).
+#define SEM_WIDE_VARIANTS(X)                                                                   \
+    X(P_F16, 1, 32) X(P_F16, 2, 32) X(P_F16, 3, 32) X(P_F16, 4, 32)                             \
+    X(P_BF16, 1, 32) X(P_BF16, 2, 32) X(P_BF16, 3, 32) X(P_BF16, 4, 32)
+
+static pass_fn find_wide(int prec, int NTW, int UR) {
+#define SEM_X(P, N, U)                                                                         \
+    if (prec == P && NTW == N && UR == U) return pass_wide_kernel<P, N, U>;
+    SEM_WIDE_VARIANTS(SEM_X)
+#undef SEM_X
+    return nullptr;
+}
+
+size_t wide_lds_bytes(int K, int Wp, int UR) { return (size_t)wide_lds(K, Wp, UR).total; }
+
+bool wide_plan(int prec, int Wp, int K, size_t lds_max, int *NTW, int *UR) {
+    const int ntw = (Wp / 16 + 3) / 4;
+    const int ur = 32;
+    if (!find_wide(prec, ntw, ur) || wide_lds_bytes(K, Wp, ur) > lds_max) return false;
+    *NTW = ntw;
+    *UR = ur;
+    return true;
+}
+
+hipError_t launch_pass_wide(int prec, int NTW, int UR, const PassArgs &a, int grid, size_t lds,
+                            hipStream_t s) {
+    pass_fn f = find_wide(prec, NTW, UR);
+    if (!f) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(f, dim3(grid), dim3(kThreads), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t pass_wide_setup(int prec, int NTW, int UR, size_t lds, int *blocks_per_cu) {
+    pass_fn f = find_wide(prec, NTW, UR);
+    if (!f) return hipErrorInvalidValue;
+    hipError_t e = hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) (void)hipGetLastError();
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void *)f, kThreads,
+                                                        lds);
+}
+
+const char *pass_wide_name(int prec, int NTW, int UR) {
+    static char buf[64];
+    snprintf(buf, sizeof buf, "pass_wide_kernel<%s,BM=%d,NTW=%d,UR=%d>", kPrecName[prec],
+             kWideBM, NTW, UR);
     return buf;
 }
 

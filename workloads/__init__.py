@@ -168,6 +168,9 @@ def observations(w: Workload, seed: int, start: int = 0, stop: Optional[int] = N
     a = image(w, seed) if a is None else a
     s2 = noise_variance(a, w.snr)
     kb = w.kbar
+    # exp(-2 pi i m / L) for every residue m, looked up per entry (the same values as evaluating
+    # it entry by entry)
+    phase = np.exp(-2j * np.pi * np.arange(w.L) / w.L)
     out = np.empty((stop - start, w.D), dtype=dtype)
     pos = 0
     for c in range(start // CHUNK, (stop - 1) // CHUNK + 1 if stop > start else start // CHUNK):
@@ -177,10 +180,35 @@ def observations(w: Workload, seed: int, start: int = 0, stop: Optional[int] = N
         l = _rotation_draw(w, _rng(seed, STREAM_ROT, c), n)[lo:hi]
         eps = _cn(_rng(seed, STREAM_NOISE, c), (n, w.D), s2)[lo:hi]
         m = (kb[None, :] * l[:, None]) % w.L
-        v = a[None, :] * np.exp(-2j * np.pi * m / w.L) + eps
+        v = a[None, :] * phase[m] + eps
         out[pos:pos + (hi - lo)] = v
         pos += hi - lo
     return out
+
+
+def observation_chunks(w: Workload, seed: int, dtype=np.complex64, a: Optional[np.ndarray] = None,
+                       workers: int = 1):
+    """Yield (first_row, rows) over the generator's chunks in order: the same values as
+    observations(), without holding all N rows at once.  workers > 1 generates chunks on that
+    many threads (the draws of every chunk come from its own seeded stream, so the values do not
+    depend on the thread count)."""
+    a = image(w, seed) if a is None else a
+    nch = (w.N + CHUNK - 1) // CHUNK
+    one = lambda c: observations(w, seed, c * CHUNK, min(w.N, (c + 1) * CHUNK), dtype=dtype, a=a)
+    if workers <= 1:
+        for c in range(nch):
+            yield c * CHUNK, one(c)
+        return
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(workers) as ex:
+        futs = {}
+        for c in range(nch):
+            while len(futs) >= 2 * workers:
+                c0 = min(futs)
+                yield c0 * CHUNK, futs.pop(c0).result()
+            futs[c] = ex.submit(one, c)
+        for c0 in sorted(futs):
+            yield c0 * CHUNK, futs[c0].result()
 
 
 def random_init(w: Workload, seed: int) -> np.ndarray:
