@@ -137,7 +137,7 @@ em_status plan(em_ctx *c, size_t lds_max) {
             c->wNTW = NTW;
             c->wUR = UR;
             c->WM = 0;
-            c->lds = wide_lds_bytes(c->K, c->Wp, UR);
+            c->lds = wide_lds_bytes(c->K, c->Wp, NTW, UR);
             return EM_OK;
         }
         return fail(c, EM_EUNSUPPORTED, "no wide-row pass variant for this window and K");
@@ -186,7 +186,7 @@ em_status plan(em_ctx *c, size_t lds_max) {
             c->wNTW = NTW;
             c->wUR = UR;
             c->WM = 0;
-            c->lds = wide_lds_bytes(c->K, c->Wp, UR);
+            c->lds = wide_lds_bytes(c->K, c->Wp, NTW, UR);
             return EM_OK;
         }
     }

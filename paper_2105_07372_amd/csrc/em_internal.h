@@ -126,7 +126,7 @@ hipError_t launch_pass_ks(int prec, int BM, int NT, int KSS, const PassArgs &a, 
 hipError_t pass_ks_setup(int prec, int BM, int NT, int KSS, size_t lds, int *blocks_per_cu);
 const char *pass_ks_name(int prec, int BM, int NT, int KSS);
 bool wide_plan(int prec, int Wp, int K, size_t lds_max, int *NTW, int *UR);
-size_t wide_lds_bytes(int K, int Wp, int UR);
+size_t wide_lds_bytes(int K, int Wp, int NTW, int UR);
 hipError_t launch_pass_wide(int prec, int NTW, int UR, const PassArgs &a, int grid, size_t lds,
                             hipStream_t s);
 hipError_t pass_wide_setup(int prec, int NTW, int UR, size_t lds, int *blocks_per_cu);

@@ -706,7 +706,15 @@ __device__ __forceinline__ void tile_wsum(const PassArgs &A, int CSW,
         const int i = tid + c * kThreads;
         if (i < A.Wp) {
             CT s = 0;
-            for (int j = 0; j < rows; ++j) s += Cs[j * CSW + i];
+            int j = 0;
+            for (; j + 8 <= rows; j += 8) {
+                CT v[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) v[t] = Cs[(j + t) * CSW + i];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) s += v[t];
+            }
+            for (; j < rows; ++j) s += Cs[j * CSW + i];
             acc.W[c] += (double)s;
         }
     }
@@ -1297,9 +1305,11 @@ constexpr int kWideKSS = 2;
 struct WideLds {
     int CSW, slot_bytes, off_u, off_f, off_lr, off_s, total;
 };
-__host__ __device__ inline WideLds wide_lds(int K, int Wp, int UR) {
+__host__ __device__ inline WideLds wide_lds(int K, int Wp, int NTW, int UR) {
     WideLds l;
-    l.CSW = Wp + 4;                                    // float4 rows, conflict-free columns
+    // 64 NTW columns (the window tiles of all wave groups; those past Wp are zero), float4
+    // rows, conflict-free columns
+    l.CSW = 64 * NTW + 4;
     l.slot_bytes = 2 * kWideKSS * kWideBM * 64;        // [half][k-step][row][64 B]
     const int ring = kWideSlots * l.slot_bytes;
     l.off_u = align_up(kWideBM * l.CSW * 4, 16);
@@ -1371,6 +1381,40 @@ __device__ __forceinline__ void wide_tload(rsrc_t Th, rsrc_t Tl, const uint32_t 
     }
 }
 
+// U (UR rows) = w . [Re E | Im E] on FP32 matrix cores with this wave's B fragments in
+// registers: wave w computes U columns 16 w .. 16 w + 15 over KGM k-steps of 4 columns of Cs
+// (columns past the window are zero).
+template <int UR, int KGM>
+__device__ __forceinline__ void u_wide_reg(const float *Cs, int CSW, const float (&ereg)[KGM],
+                                           int K, const float *rowu, float2 *Us, int ucol) {
+    constexpr int MS = UR / 16;
+    const int lane = threadIdx.x & 63, g = lane >> 4, rl = lane & 15;
+    if ((threadIdx.x >> 6) * 16 >= 2 * K) return;
+    f32x4 acc[MS];
+#pragma unroll
+    for (int m = 0; m < MS; ++m) acc[m] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < KGM; ++kk)
+#pragma unroll
+        for (int m = 0; m < MS; ++m) {
+            const float a = Cs[(m * 16 + rl) * CSW + kk * 4 + g];
+            acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, ereg[kk], acc[m], 0, 0, 0);
+        }
+    if (ucol < 2 * K) {
+#pragma unroll
+        for (int m = 0; m < MS; ++m)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = m * 16 + 4 * g + q;
+                const float v = acc[m][q] * rowu[row];
+                if (ucol < K)
+                    Us[row * K + ucol].x = v;
+                else
+                    Us[row * K + ucol - K].y = v;
+            }
+    }
+}
+
 template <int P, int NTW, int UR>
 __global__ __launch_bounds__(kThreads) void pass_wide_kernel(PassArgs A) {
     static_assert(P == P_F16 || P == P_BF16, "one 16-bit observation plane");
@@ -1384,7 +1428,7 @@ __global__ __launch_bounds__(kThreads) void pass_wide_kernel(PassArgs A) {
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform, in an SGPR
     const int g = lane >> 4, c = lane & 15;
-    const WideLds LY = wide_lds(A.K, A.Wp, UR);
+    const WideLds LY = wide_lds(A.K, A.Wp, NTW, UR);
     float *Cs = (float *)smem;
     float2 *Us = (float2 *)(smem + LY.off_u);
     float *rowf = (float *)(smem + LY.off_f);
@@ -1509,7 +1553,13 @@ __global__ __launch_bounds__(kThreads) void pass_wide_kernel(PassArgs A) {
 #pragma unroll
             for (int n = 0; n < NTW; ++n) {
                 const int nt = iw + 4 * n;
-                if (nt >= NT) continue;
+                if (nt >= NT) {                        // zero columns past the window tiles
+#pragma unroll
+                    for (int m = 0; m < MJ; ++m)
+                        *(f32x4 *)(Cs + (16 * m + c) * LY.CSW + 16 * nt + 4 * g) =
+                            (f32x4){0.f, 0.f, 0.f, 0.f};
+                    continue;
+                }
                 const f32x4 lr4 = *(const f32x4 *)(lrs + 16 * nt + 4 * g);
 #pragma unroll
                 for (int m = 0; m < MJ; ++m) {
@@ -1534,39 +1584,86 @@ __global__ __launch_bounds__(kThreads) void pass_wide_kernel(PassArgs A) {
         if (!(A.flags & PF_ACC_M)) continue;
         __syncthreads();
         tile_wsum<P, DPT>(A, LY.CSW, Cs, rows, acc);
+        // B fragments of U = w [Re E | Im E] for this wave's 16-column tile of U, in registers
+        // for the whole tile (one column tile per wave when 2K <= 128)
+        const bool ureg = 2 * A.K <= 16 * (kThreads / 64);
+        const int ucol = wave * 16 + c;
+        constexpr int KGM = 16 * NTW;                  // 4-column k-steps over 64 NTW columns
+        float ereg[KGM];
+        if (ureg) {
+            // E2 row 4 kk + g, column ucol; rows past Wp are clamped (they meet zero
+            // posteriors) and so are columns past 2K (their U columns are not stored)
+            const rsrc_t Er = make_rsrc(A.E2, (uint32_t)(A.Wp * 2 * A.K * 4));
+            const int ccol = ucol < 2 * A.K ? ucol : 2 * A.K - 1;
+#pragma unroll
+            for (int kk = 0; kk < KGM; ++kk) {
+                const int row = 4 * kk + g < A.Wp ? 4 * kk + g : A.Wp - 1;
+                ereg[kk] = __builtin_bit_cast(
+                    float, __builtin_amdgcn_raw_buffer_load_b32(
+                               Er, (uint32_t)(row * 2 * A.K + ccol) * 4u, 0u, 0));
+            }
+        }
         for (int rc = 0; rc < rows; rc += UR) {
             if (rc) __syncthreads();                   // the previous chunk's U is consumed
-            u_mfma<UR>(Cs + rc * LY.CSW, LY.CSW, A.E2, A.Wp, A.K, rowu + rc, Us);
+            if (ureg)
+                u_wide_reg<UR, KGM>(Cs + rc * LY.CSW, LY.CSW, ereg, A.K, rowu + rc, Us, ucol);
+            else
+                u_mfma<UR>(Cs + rc * LY.CSW, LY.CSW, A.E2, A.Wp, A.K, rowu + rc, Us);
             __syncthreads();
             const int nr = rows - rc < UR ? rows - rc : UR;
             const uint8_t *vb = A.V + (r0 + rc) * A.rowbytes;
-#pragma unroll
-            for (int cc = 0; cc < DPT; ++cc) {
-                const int d = tid + cc * kThreads;
-                if (d >= A.D) continue;
-                const int k = d / A.Q;
-                float sr = 0.f, si = 0.f;
+            // M-step: thread t owns the four entries 4t .. 4t+3 (16 bytes of every row), with
+            // 8 rows of loads in flight
+            const int d0 = 4 * tid;
+            if (d0 < A.D) {
+                const int k0 = d0 / A.Q, k3 = (d0 + 3) / A.Q;
+                float sr[4] = {0.f, 0.f, 0.f, 0.f}, si[4] = {0.f, 0.f, 0.f, 0.f};
                 for (int j0 = 0; j0 < nr; j0 += 8) {
-                    float2 v[8];
+                    u32x4 raw[8];
 #pragma unroll
                     for (int t = 0; t < 8; ++t) {
                         const int j = j0 + t < nr ? j0 + t : nr - 1;
-                        v[t] = load_v<P>(vb + (int64_t)j * A.rowbytes, d, A.Dp);
+                        raw[t] = *(const u32x4 *)(vb + (int64_t)j * A.rowbytes + 16 * tid);
                     }
 #pragma unroll
                     for (int t = 0; t < 8; ++t) {
-                        if (j0 + t < nr) {
-                            const float2 u = Us[(j0 + t) * A.K + k];
-                            sr += u.x * v[t].x - u.y * v[t].y;
-                            si += u.x * v[t].y + u.y * v[t].x;
+                        if (j0 + t >= nr) break;
+                        const float2 *ur = Us + (j0 + t) * A.K;
+                        float2 u[4];
+                        u[0] = ur[k0];
+                        if (k3 == k0) {
+                            u[1] = u[2] = u[3] = u[0];
+                        } else {
+#pragma unroll
+                            for (int e = 1; e < 4; ++e) u[e] = ur[(d0 + e) / A.Q];
+                        }
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            float vr, vi;
+                            if constexpr (P == P_F16) {
+                                const _Float16 *h = (const _Float16 *)&raw[t];
+                                vr = (float)h[2 * e];
+                                vi = (float)h[2 * e + 1];
+                            } else {
+                                const __bf16 *h = (const __bf16 *)&raw[t];
+                                vr = (float)h[2 * e];
+                                vi = (float)h[2 * e + 1];
+                            }
+                            sr[e] += u[e].x * vr - u[e].y * vi;
+                            si[e] += u[e].x * vi + u[e].y * vr;
                         }
                     }
                 }
-                Sacc[d].x += (double)sr;
-                Sacc[d].y += (double)si;
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (d0 + e < A.D) {
+                        Sacc[d0 + e].x += (double)sr[e];
+                        Sacc[d0 + e].y += (double)si[e];
+                    }
             }
         }
     }
+    __syncthreads();                                   // Sacc rows were written by other waves
 #pragma unroll
     for (int cc = 0; cc < DPT; ++cc) acc.S[cc] = Sacc[tid + cc * kThreads];
     __syncthreads();
@@ -1974,12 +2071,14 @@ static pass_fn find_wide(int prec, int NTW, int UR) {
     return nullptr;
 }
 
-size_t wide_lds_bytes(int K, int Wp, int UR) { return (size_t)wide_lds(K, Wp, UR).total; }
+size_t wide_lds_bytes(int K, int Wp, int NTW, int UR) {
+    return (size_t)wide_lds(K, Wp, NTW, UR).total;
+}
 
 bool wide_plan(int prec, int Wp, int K, size_t lds_max, int *NTW, int *UR) {
     const int ntw = (Wp / 16 + 3) / 4;
     const int ur = 32;
-    if (!find_wide(prec, ntw, ur) || wide_lds_bytes(K, Wp, ur) > lds_max) return false;
+    if (!find_wide(prec, ntw, ur) || wide_lds_bytes(K, Wp, ntw, ur) > lds_max) return false;
     *NTW = ntw;
     *UR = ur;
     return true;
