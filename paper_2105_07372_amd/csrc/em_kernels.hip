@@ -363,6 +363,27 @@ __device__ __forceinline__ typename PT<P>::CT2 load_v(const uint8_t *row, int d,
     }
 }
 
+// The same entry read as whole 32-bit words (bf16 widened by a shift): for the M-step loops.
+template <int P>
+__device__ __forceinline__ float2 load_v32(const uint8_t *row, int d, int Dp) {
+    if constexpr (P == P_F32) {
+        return *(const float2 *)(row + 8 * d);
+    } else if constexpr (P == P_F16) {
+        const uint32_t w = *(const uint32_t *)(row + 4 * d);
+        const _Float16 *h = (const _Float16 *)&w;
+        return make_float2((float)h[0], (float)h[1]);
+    } else {
+        const uint32_t w = *(const uint32_t *)(row + 4 * d);
+        float re = __uint_as_float(w << 16), im = __uint_as_float(w & 0xffff0000u);
+        if constexpr (P == P_BF16X3) {
+            const uint32_t l = *(const uint32_t *)(row + 2 * Dp + 4 * d);
+            re += __uint_as_float(l << 16);
+            im += __uint_as_float(l & 0xffff0000u);
+        }
+        return make_float2(re, im);
+    }
+}
+
 // Correlations of MSW 16-row blocks (rows (wm + m WM) 16 ..) with up to NTW 16-column tiles
 // (nt0, nt0 + WN, ...) of the template, MFMA paths.  A fragments come from the LDS tile, B
 // fragments stream from L2 through a ring of PD k-steps in registers.
@@ -592,12 +613,22 @@ __device__ __forceinline__ void u_mfma_reg(const float *Cs, int CSW, const float
 #pragma unroll
     for (int m = 0; m < MS; ++m) acc[m] = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int kk = 0; kk < KG; ++kk)
+    for (int k0 = 0; k0 < KG; k0 += 4) {
+        float a[4][MS];                            // four k-steps of A reads before the MFMAs
 #pragma unroll
-        for (int m = 0; m < MS; ++m) {
-            const float a = Cs[(m * 16 + rl) * CSW + kk * 4 + g];
-            acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, ereg[kk], acc[m], 0, 0, 0);
-        }
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int m = 0; m < MS; ++m)
+                a[t][m] = (k0 + t < KG) ? Cs[(m * 16 + rl) * CSW + (k0 + t) * 4 + g] : 0.f;
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int m = 0; m < MS; ++m)
+                if (k0 + t < KG)
+                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][m], ereg[k0 + t], acc[m],
+                                                                  0, 0, 0);
+    }
     if (ucol < 2 * K) {
 #pragma unroll
         for (int m = 0; m < MS; ++m)
@@ -688,7 +719,7 @@ __device__ __forceinline__ void tile_rows(const PassArgs &A, int CSW, typename P
         }
         if (sub == 0 && valid) {
             acc.lse += (double)lse;
-            acc.wc += (double)wc / A.coef;            // sum_i w_ji C_ji
+            acc.wc += (double)wc;                     // sum_i w_ji (l_ji - log rho_i)
             acc.rows += 1.0;
             if (A.flags & PF_STORE_LSE) A.lse[r0 + r] = (double)lse;
         }
@@ -765,7 +796,12 @@ __device__ __forceinline__ void tile_post(const PassArgs &A, const PassLds &LY, 
             const int k = d / A.Q;
             CT sr = 0, si = 0;
             for (int j = 0; j < rows; ++j) {
-                const CT2 v = load_v<P>(Vs + j * LY.RS, d, A.Dp);
+                CT2 v;
+                if constexpr (P == P_F64) {
+                    v = load_v<P>(Vs + j * LY.RS, d, A.Dp);
+                } else {
+                    v = load_v32<P>(Vs + j * LY.RS, d, A.Dp);
+                }
                 const CT2 u = Us[j * A.K + k];
                 sr += u.x * v.x - u.y * v.y;
                 si += u.x * v.y + u.y * v.x;
@@ -805,7 +841,7 @@ __device__ __forceinline__ void write_partials(const PassArgs &A, PassAcc<DPT> &
     const double s_rows = block_sum_d(acc.rows, sh, kThreads);
     if (tid == 0) {
         Pp[2 * A.D + A.Wp] = s_lse;
-        Pp[2 * A.D + A.Wp + 1] = s_wc;
+        Pp[2 * A.D + A.Wp + 1] = s_wc / A.coef;         // sum_j sum_i w_ji C_ji
         Pp[2 * A.D + A.Wp + 2] = s_rows;
         Pp[2 * A.D + A.Wp + 3] = 0.0;
     }
@@ -956,7 +992,7 @@ struct KsLds {
 __host__ __device__ inline KsLds ks_lds(int prec, int BM, int NT, int K, int Dp, int Wp) {
     KsLds l;
     l.RS = (int)row_bytes(prec, Dp) + 16;
-    l.CSW = Wp + 1;
+    l.CSW = Wp + 4;                                         // conflict-free U operand reads
     l.off_v1 = align_up(BM * l.RS, 16);                     // second tile buffer
     l.off_red = align_up(2 * BM * l.RS, 16);
     l.off_c = align_up(l.off_red + 4 * (BM / 16) * NT * 64 * 16, 16);
@@ -1043,7 +1079,7 @@ __device__ __forceinline__ void ks_post(const PassArgs &A, const KsLds &LY, cons
         wsum += w;
         if (lane == 0 && rval) {
             acc.lse += (double)lse;
-            acc.wc += (double)wc / A.coef;
+            acc.wc += (double)wc;
             acc.rows += 1.0;
             if (A.flags & PF_STORE_LSE) A.lse[r0 + r] = (double)lse;
         }
@@ -1053,6 +1089,8 @@ __device__ __forceinline__ void ks_post(const PassArgs &A, const KsLds &LY, cons
     __syncthreads();
     u_mfma_reg<BM, KG>(Cs, LY.CSW, ereg, A.K, rowu, Us, uact, ucol);
     __syncthreads();
+    // M-step: S_d += sum_j U_{j, kbar_d} v_jd, all BM rows unconditionally (rows past the
+    // tile's end are masked by a select, so stale LDS contents cannot leak in)
 #pragma unroll
     for (int c = 0; c < DPT; ++c) {
         const int d = tid + c * kThreads;
@@ -1060,12 +1098,19 @@ __device__ __forceinline__ void ks_post(const PassArgs &A, const KsLds &LY, cons
             const int k = d / A.Q;
             float sr = 0.f, si = 0.f;
 #pragma unroll
-            for (int j = 0; j < BM; ++j) {
-                if (j < rows) {
-                    const float2 v = load_v<P>(Vs + j * LY.RS, d, A.Dp);
-                    const float2 u = Us[j * A.K + k];
-                    sr += u.x * v.x - u.y * v.y;
-                    si += u.x * v.y + u.y * v.x;
+            for (int j0 = 0; j0 < BM; j0 += 4) {
+                float2 v[4], u[4];                 // four rows of loads before any arithmetic
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    v[t] = load_v32<P>(Vs + (j0 + t) * LY.RS, d, A.Dp);
+                    u[t] = Us[(j0 + t) * A.K + k];
+                }
+                asm volatile("" ::: "memory");
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const bool ok = j0 + t < rows;
+                    sr += ok ? u[t].x * v[t].x - u[t].y * v[t].y : 0.f;
+                    si += ok ? u[t].x * v[t].y + u[t].y * v[t].x : 0.f;
                 }
             }
             acc.S[c].x += (double)sr;
