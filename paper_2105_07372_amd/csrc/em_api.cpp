@@ -42,6 +42,8 @@ struct em_ctx {
     int ksNT = 0, ksKSS = 0;
     bool wide = false;    // wide-row pass (rows streamed through an LDS ring, 128-row tiles)
     int wNTW = 0, wUR = 0;
+    bool fac = false;     // factored pass (per-frequency sums; no template)
+    int fWIDE = 0, fKCM = 0;
     int64_t rowbytes = 0;
     size_t lds = 0;
     hipStream_t stream = nullptr;
@@ -128,6 +130,23 @@ int pow2_floor(int x) {
 em_status plan(em_ctx *c, size_t lds_max) {
     c->ks = false;
     c->wide = false;
+    c->fac = false;
+    if (c->flags & EM_FLAG_FACTORED) {
+        int WIDE = 0, KCM = 0;
+        size_t lds = 0;
+        if (c->prec != P_F64 && fac_plan(c->prec, c->D, c->Q, c->K, c->Wp, lds_max, &WIDE, &KCM, &lds)) {
+            c->fac = true;
+            c->BM = kFacBMH;
+            c->fWIDE = WIDE;
+            c->fKCM = KCM;
+            c->WM = 0;
+            c->lds = lds;
+            return EM_OK;
+        }
+        return fail(c, EM_EUNSUPPORTED,
+                    "the factored pass needs D = 512, Q a power-of-two multiple of 8 and a "
+                    "matrix-core precision");
+    }
     const bool one_plane = c->prec == P_F16 || c->prec == P_BF16;
     if (one_plane && (c->flags & EM_FLAG_WIDE_PASS)) {
         int NTW = 0, UR = 0;
@@ -221,7 +240,7 @@ em_status check_params(const em_params *p) {
     if (p->precision < EM_FP64 || p->precision > EM_BF16)
         return fail(nullptr, EM_EINVAL, "unknown precision");
     if (p->flags & ~(uint64_t)(EM_FLAG_KEEP_LSE | EM_FLAG_TIMING | EM_FLAG_GENERAL_PASS |
-                               EM_FLAG_WIDE_PASS))
+                               EM_FLAG_WIDE_PASS | EM_FLAG_FACTORED))
         return fail(nullptr, EM_EINVAL, "unknown flag bits");
     if (p->window_lo < -(1 << 30) || p->window_lo > (1 << 30))
         return fail(nullptr, EM_EINVAL, "window_lo out of range");
@@ -308,6 +327,8 @@ em_status run_pass(em_ctx *c, int flags, int64_t r0, int64_t r1, const double *a
         HIPCHK(c, launch_pass_ks(c->prec, c->BM, c->ksNT, c->ksKSS, A, grid, c->lds, c->stream));
     else if (c->wide)
         HIPCHK(c, launch_pass_wide(c->prec, c->wNTW, c->wUR, A, grid, c->lds, c->stream));
+    else if (c->fac)
+        HIPCHK(c, launch_pass_fac(c->prec, c->fWIDE, c->fKCM, A, grid, c->lds, c->stream));
     else
         HIPCHK(c, launch_pass(c->prec, c->BM, c->WM, c->LD, A, grid, c->lds, c->stream));
     if (ev) {
@@ -458,6 +479,11 @@ em_status em_init(em_ctx **out, const em_params *p, const void *obs_dev, const d
         }
     } else if (c->wide) {
         if (pass_wide_setup(c->prec, c->wNTW, c->wUR, c->lds, &occ) != hipSuccess || occ < 1) {
+            (void)hipGetLastError();
+            occ = 1;
+        }
+    } else if (c->fac) {
+        if (pass_fac_setup(c->prec, c->fWIDE, c->fKCM, c->lds, &occ) != hipSuccess || occ < 1) {
             (void)hipGetLastError();
             occ = 1;
         }
@@ -629,7 +655,7 @@ em_status em_step(em_ctx *c, int32_t n_iter, double tol, int32_t *iters_done, do
         if (st != EM_OK) return st;
         HIPCHK(c, launch_reduce(c->partials, c->grid, c->ncols, c->red, c->stream));
         HIPCHK(c, launch_finalize(F, c->stream));
-        if (!c->ks)      // the K-split pass builds its template from a_t itself
+        if (!c->ks && !c->fac)   // these passes use a_t itself
             if ((st = run_template(c, c->a, c->Thi, c->Tlo, c->tscale, true)) != EM_OK) return st;
     }
     if (iters_done || ll_last) {
@@ -851,6 +877,7 @@ em_status em_get_info(const em_ctx *c, em_info *info) {
     std::snprintf(info->kernel, sizeof info->kernel, "%s",
                   c->ks     ? pass_ks_name(c->prec, c->BM, c->ksNT, c->ksKSS)
                   : c->wide ? pass_wide_name(c->prec, c->wNTW, c->wUR)
+                  : c->fac  ? pass_fac_name(c->prec, c->fWIDE, c->fKCM)
                             : pass_kernel_name(c->prec, c->BM, c->WM, c->LD));
     return EM_OK;
 }

@@ -1716,6 +1716,278 @@ __global__ __launch_bounds__(kThreads) void pass_wide_kernel(PassArgs A) {
 }
 
 // ------------------------------------------------------------------------------------------
+// Factored E(+M) pass: the correlations through per-frequency sums, an exact rewrite of the
+// contraction (a rotation is one phase per angular frequency, §I eq. (3)):
+//   Re <v_j, R_{o_i} a> = Re sum_k c_jk exp(-i k theta_i),   c_jk = sum_q conj(v_jkq) a_kq.
+// Per row this costs 4D + 4KW flops instead of 4DW, no template exists, and the pass is a stream
+// over the rows.  Each wave owns kFacRPW rows of a tile of kFacBM rows and holds them in
+// registers (lane l: entries 8l .. 8l+7, so D = 512; Q/8 lanes share an angular frequency),
+// while the next tile's rows load.  c goes to LDS; C = [Re c | Im c] . [cos; sin] and
+// U = w [Re E | Im E] are FP32 matrix-core products against the phase table (fragments in
+// registers when Wp <= 64, streamed from L2 otherwise); the posteriors as in the other passes;
+// the M-step from the rows in registers, the eight waves' partial sums added in wave order into
+// per-entry FP64 accumulators.
+
+constexpr int kFacRPW = 4;                    // rows per wave per tile
+constexpr int kFacBM = 8 * kFacRPW;           // rows per tile
+static_assert(kFacBM == kFacBMH, "host and device tile sizes");
+constexpr int kFacEPL = 8;                    // entries per lane: D = 64 kFacEPL
+
+struct FacLds {
+    int CBW, CSW, off_cs, off_u, off_sw, off_f, off_lr, off_a, total;
+};
+__host__ __device__ inline FacLds fac_lds(int K, int D, int Wp, int KCM) {
+    FacLds l;
+    l.CBW = 4 * KCM + 4;                       // [Re c | Im c | 0 ..], conflict-free A reads
+    l.CSW = (Wp > 64 ? Wp : 64) + 4;           // columns past Wp stay zero (register U path)
+    l.off_cs = align_up(kFacBM * l.CBW * 4, 16);
+    l.off_u = align_up(l.off_cs + kFacBM * l.CSW * 4, 16);
+    l.off_sw = align_up(l.off_u + kFacBM * K * 8, 16);
+    l.off_f = align_up(l.off_sw + 8 * D * 8, 16);
+    l.off_lr = l.off_f + 2 * kFacBM * 4;
+    l.off_a = align_up(l.off_lr + Wp * 4, 16);
+    l.total = l.off_a + D * 8;
+    return l;
+}
+
+// Words of one stored row for lane l (entries 8l .. 8l+7): FP32 16 words (re, im per entry);
+// bf16x3 8 hi words then 8 lo words; fp16 / bf16 8 words.
+template <int P>
+struct FacRow {
+    static constexpr int WPL = (P == P_F32 || P == P_BF16X3) ? 16 : 8;
+    u32x4 w[WPL / 4];
+    __device__ __forceinline__ void load(const uint8_t *row, int Dp, int lane) {
+        if constexpr (P == P_F32) {
+            const u32x4 *p = (const u32x4 *)(row + 64 * lane);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) w[t] = p[t];
+        } else {
+            const u32x4 *p = (const u32x4 *)(row + 32 * lane);
+            w[0] = p[0];
+            w[1] = p[1];
+            if constexpr (P == P_BF16X3) {
+                const u32x4 *q = (const u32x4 *)(row + 2 * Dp + 32 * lane);
+                w[2] = q[0];
+                w[3] = q[1];
+            }
+        }
+    }
+    __device__ __forceinline__ float2 entry(int e) const {
+        if constexpr (P == P_F32) {
+            return make_float2(__uint_as_float(w[e >> 1][(e & 1) * 2]),
+                               __uint_as_float(w[e >> 1][(e & 1) * 2 + 1]));
+        } else if constexpr (P == P_F16) {
+            const uint32_t x = w[e >> 2][e & 3];
+            const _Float16 *h = (const _Float16 *)&x;
+            return make_float2((float)h[0], (float)h[1]);
+        } else {
+            const uint32_t x = w[e >> 2][e & 3];
+            float re = __uint_as_float(x << 16), im = __uint_as_float(x & 0xffff0000u);
+            if constexpr (P == P_BF16X3) {
+                const uint32_t y = w[2 + (e >> 2)][e & 3];
+                re += __uint_as_float(y << 16);
+                im += __uint_as_float(y & 0xffff0000u);
+            }
+            return make_float2(re, im);
+        }
+    }
+};
+
+// WIDE = 0: Wp <= 64 (phase fragments in registers); 1: longer windows.  KCM = k-steps of 4
+// columns over [Re c | Im c] (2K <= 4 KCM).
+template <int P, int WIDE, int KCM>
+__global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
+    static_assert(P != P_F64, "matrix-core precisions");
+    constexpr int BM = kFacBM, RPW = kFacRPW, EPL = kFacEPL, DPT = 1;   // D = 512 = threads
+    if ((A.flags & PF_CHECK_STOP) && *A.stopped) return;
+
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int g = lane >> 4, c = lane & 15;
+    const int K = A.K, D = A.D, Wp = A.Wp, NT = Wp / 16;
+    const FacLds LY = fac_lds(K, D, Wp, KCM);
+    float *cb = (float *)smem;
+    float *Cs = (float *)(smem + LY.off_cs);
+    float2 *Us = (float2 *)(smem + LY.off_u);
+    float2 *Sw = (float2 *)(smem + LY.off_sw);
+    float *rowf = (float *)(smem + LY.off_f);
+    float *rowu = rowf + BM;
+    float *lrs = (float *)(smem + LY.off_lr);
+    float2 *as = (float2 *)(smem + LY.off_a);                 // a (FP32), D entries
+    for (int i = tid; i < Wp; i += kThreads) lrs[i] = A.logrho32[i];
+    for (int d = tid; d < D; d += kThreads)
+        as[d] = make_float2((float)A.a[2 * d], (float)A.a[2 * d + 1]);
+
+    // this lane's entries and their coefficients a (FP32), its angular frequency and lane group
+    const int d0 = EPL * lane;
+    const int LPK = A.Q / EPL;
+    const int kl = d0 / A.Q;
+    __syncthreads();
+    // C product: wave w computes rows 16 (w >> 2) .. of window tile (w & 3) (Wp <= 64); its B
+    // fragments E2[16 n + c][4 kk + g] (zero past 2K)
+    float cfr[KCM];
+    const int cm = wave >> 2, cn = wave & 3;
+    if constexpr (!WIDE) {
+#pragma unroll
+        for (int kk = 0; kk < KCM; ++kk) {
+            const int col = 4 * kk + g, i = 16 * cn + c;
+            cfr[kk] = (col < 2 * K && i < Wp) ? A.E2[(int64_t)i * 2 * K + col] : 0.f;
+        }
+    }
+    // U product: wave w computes U columns 16 w + c over 16 k-steps (Wp <= 64)
+    const int ucol = wave * 16 + c;
+    float ereg[16];
+    if constexpr (!WIDE) {
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            const int i = 4 * kk + g;
+            ereg[kk] = (i < Wp && ucol < 2 * K) ? A.E2[(int64_t)i * 2 * K + ucol] : 0.f;
+        }
+    }
+
+    PassAcc<DPT> acc;
+    acc.init();
+    const int64_t ntiles = (A.row_end - A.row_begin + BM - 1) / BM;
+    FacRow<P> vn[RPW];
+    float rsn[RPW];
+    auto load_tile = [&](int64_t t) {
+        const int64_t rb = A.row_begin + t * BM + RPW * wave;
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+            const int64_t row = rb + r < A.row_end ? rb + r : A.row_end - 1;
+            vn[r].load(A.V + row * A.rowbytes, A.Dp, lane);
+            rsn[r] = A.rowscale ? A.rowscale[row] : 1.0f;
+        }
+    };
+    int64_t tile = blockIdx.x;
+    if (tile < ntiles) load_tile(tile);
+    for (; tile < ntiles; tile += gridDim.x) {
+        const int64_t r0 = A.row_begin + tile * BM;
+        const int rows = (int)((A.row_end - r0) < BM ? (A.row_end - r0) : BM);
+        FacRow<P> vc[RPW];
+        float rsc[RPW];
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+            vc[r] = vn[r];
+            rsc[r] = rsn[r];
+        }
+        if (tile + gridDim.x < ntiles) load_tile(tile + gridDim.x);
+
+        // ---- c_jk for this wave's rows; row factors
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+            const int j = RPW * wave + r;
+            float cr = 0.f, ci = 0.f;
+#pragma unroll
+            for (int e = 0; e < EPL; ++e) {
+                const float2 v = vc[r].entry(e);
+                const float2 av = as[d0 + e];
+                cr += v.x * av.x + v.y * av.y;            // Re conj(v) a
+                ci += v.x * av.y - v.y * av.x;            // Im conj(v) a
+            }
+            for (int o = 1; o < LPK; o <<= 1) {
+                cr += __shfl_xor(cr, o);
+                ci += __shfl_xor(ci, o);
+            }
+            if ((lane & (LPK - 1)) == 0) {
+                cb[j * LY.CBW + kl] = cr;
+                cb[j * LY.CBW + K + kl] = ci;
+            }
+            for (int col = 2 * K + lane; col < 4 * KCM; col += 64) cb[j * LY.CBW + col] = 0.f;
+            if (lane == 0) {
+                const float u = j < rows ? rsc[r] : 1.0f;
+                rowf[j] = (float)A.coef * u;
+                rowu[j] = u;
+            }
+        }
+        __syncthreads();
+
+        // ---- C = [Re c | Im c] . E2^T on FP32 matrix cores -> l' = coef C / s_j + log rho
+        if constexpr (!WIDE) {
+            f32x4 cacc = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kk = 0; kk < KCM; ++kk) {
+                const float a = cb[(16 * cm + c) * LY.CBW + 4 * kk + g];
+                cacc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, cfr[kk], cacc, 0, 0, 0);
+            }
+            const int col = 16 * cn + c;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = 16 * cm + 4 * g + q;
+                Cs[row * LY.CSW + col] = cn < NT ? cacc[q] * rowf[row] + lrs[col] : 0.f;
+            }
+        } else {
+            for (int p = wave; p < 2 * NT; p += 8) {
+                const int m = p & 1, n = p >> 1;
+                f32x4 cacc = (f32x4){0.f, 0.f, 0.f, 0.f};
+                const float *eb = A.E2 + (int64_t)(16 * n + c) * 2 * K;
+#pragma unroll
+                for (int kk = 0; kk < KCM; ++kk) {
+                    const int colk = 4 * kk + g;
+                    const float b = colk < 2 * K ? eb[colk] : 0.f;
+                    const float a = cb[(16 * m + c) * LY.CBW + colk];
+                    cacc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, cacc, 0, 0, 0);
+                }
+                const int col = 16 * n + c;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row = 16 * m + 4 * g + q;
+                    Cs[row * LY.CSW + col] = cacc[q] * rowf[row] + lrs[col];
+                }
+            }
+        }
+        __syncthreads();
+
+        // ---- a4 + a5
+        tile_rows<P, BM, DPT>(A, LY.CSW, Cs, lrs, r0, rows, acc);
+        if (!(A.flags & PF_ACC_M)) continue;
+        __syncthreads();
+        tile_wsum<P, DPT>(A, LY.CSW, Cs, rows, acc);
+        if constexpr (!WIDE)
+            u_wide_reg<BM, 16>(Cs, LY.CSW, ereg, K, rowu, Us, ucol);
+        else
+            u_mfma<BM>(Cs, LY.CSW, A.E2, Wp, K, rowu, Us);
+        __syncthreads();
+        // M-step from the rows in registers: this lane's entries over this wave's rows
+        float sr[EPL], si[EPL];
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) sr[e] = si[e] = 0.f;
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+            const int j = RPW * wave + r;
+            const float2 u = j < rows ? Us[j * K + kl] : make_float2(0.f, 0.f);
+#pragma unroll
+            for (int e = 0; e < EPL; ++e) {
+                const float2 v = vc[r].entry(e);
+                sr[e] += u.x * v.x - u.y * v.y;
+                si[e] += u.x * v.y + u.y * v.x;
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) Sw[wave * D + d0 + e] = make_float2(sr[e], si[e]);
+        __syncthreads();
+#pragma unroll
+        for (int cc = 0; cc < DPT; ++cc) {
+            const int d = tid + cc * kThreads;
+            if (d < D) {
+                float2 s = Sw[d];
+#pragma unroll
+                for (int w = 1; w < 8; ++w) {
+                    const float2 t = Sw[w * D + d];
+                    s.x += t.x;
+                    s.y += t.y;
+                }
+                acc.S[cc].x += (double)s.x;
+                acc.S[cc].y += (double)s.y;
+            }
+        }
+    }
+    __syncthreads();
+    if (A.partials) write_partials(A, acc, smem);
+}
+
+// ------------------------------------------------------------------------------------------
 // a6: FP64 finalize (one workgroup of kFinThreads).
 
 constexpr int kFinThreads = 512;
@@ -2151,6 +2423,62 @@ const char *pass_wide_name(int prec, int NTW, int UR) {
     static char buf[64];
     snprintf(buf, sizeof buf, "pass_wide_kernel<%s,BM=%d,NTW=%d,UR=%d>", kPrecName[prec],
              kWideBM, NTW, UR);
+    return buf;
+}
+
+// Factored variants: (precision, window > 64, k-steps over [Re c | Im c]).
+#define SEM_FAC_VARIANTS(X)                                                                    \
+    X(P_F32, 0, 16) X(P_F32, 1, 16) X(P_F32, 0, 32) X(P_F32, 1, 32)                             \
+    X(P_BF16X3, 0, 16) X(P_BF16X3, 1, 16) X(P_BF16X3, 0, 32) X(P_BF16X3, 1, 32)                 \
+    X(P_F16, 0, 16) X(P_F16, 1, 16) X(P_F16, 0, 32) X(P_F16, 1, 32)                             \
+    X(P_BF16, 0, 16) X(P_BF16, 1, 16) X(P_BF16, 0, 32) X(P_BF16, 1, 32)
+
+static pass_fn find_fac(int prec, int WIDE, int KCM) {
+#define SEM_X(P, Wd, KC)                                                                       \
+    if (prec == P && WIDE == Wd && KCM == KC) return pass_fac_kernel<P, Wd, KC>;
+    SEM_FAC_VARIANTS(SEM_X)
+#undef SEM_X
+    return nullptr;
+}
+
+bool fac_plan(int prec, int D, int Q, int K, int Wp, size_t lds_max, int *WIDE, int *KCM,
+              size_t *lds) {
+    if (D != 64 * kFacEPL || Q % kFacEPL != 0) return false;
+    const int lpk = Q / kFacEPL;
+    if (lpk & (lpk - 1)) return false;                       // lanes per frequency: 2^n
+    const int kcm = 2 * K <= 64 ? 16 : (2 * K <= 128 ? 32 : 0);
+    const int wide = Wp > 64 ? 1 : 0;
+    if (!kcm || !find_fac(prec, wide, kcm)) return false;
+    const size_t b = (size_t)fac_lds(K, D, Wp, kcm).total;
+    if (b > lds_max) return false;
+    *WIDE = wide;
+    *KCM = kcm;
+    *lds = b;
+    return true;
+}
+
+hipError_t launch_pass_fac(int prec, int WIDE, int KCM, const PassArgs &a, int grid, size_t lds,
+                           hipStream_t s) {
+    pass_fn f = find_fac(prec, WIDE, KCM);
+    if (!f) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(f, dim3(grid), dim3(kThreads), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t pass_fac_setup(int prec, int WIDE, int KCM, size_t lds, int *blocks_per_cu) {
+    pass_fn f = find_fac(prec, WIDE, KCM);
+    if (!f) return hipErrorInvalidValue;
+    hipError_t e = hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) (void)hipGetLastError();
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void *)f, kThreads,
+                                                        lds);
+}
+
+const char *pass_fac_name(int prec, int WIDE, int KCM) {
+    static char buf[64];
+    snprintf(buf, sizeof buf, "pass_fac_kernel<%s,BM=%d,%s,KC=%d>", kPrecName[prec], kFacBM,
+             WIDE ? "L2" : "reg", KCM);
     return buf;
 }
 

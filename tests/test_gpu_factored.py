@@ -1,0 +1,136 @@
+"""The factored E(+M) pass (correlations through the per-frequency sums c_jk, an exact rewrite of
+the contraction; no template) against the FP64 oracle: teacher-forced steps on windowed and
+full-search shapes with one, two and four lanes per angular frequency and ragged row tails, every
+precision it supports; a windowed trajectory; the posterior queries and the adjoint."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": dict(post=2e-4, a=2e-5, ll=1e-7), "bf16x3": dict(post=1e-3, a=1e-4, ll=1e-6),
+       "fp16": dict(post=1e-3, a=2e-4, ll=1e-6), "bf16": dict(post=5e-3, a=1e-3, ll=1e-5)}
+
+SHAPES = {
+    # name: (K, Q, L, half window (None: full search), N)
+    "win16": (32, 16, 360, 24, 4099),      # the windowed workload's shape: W = 49
+    "win8": (64, 8, 72, 6, 1001),          # one lane per frequency, W = 13
+    "win32": (16, 32, 360, 40, 777),       # four lanes per frequency, W = 81 (L2 path)
+    "full": (32, 16, 60, None, 2050),      # full search, W = 60
+}
+
+
+def _problem(shape, seed=0):
+    K, Q, L, h, N = SHAPES[shape]
+    base = wl.WORKLOADS["c3"] if h is not None else wl.WORKLOADS["c2"]
+    w = base.replace(K=K, Q=Q, L=L, N=N, **({"half_window": h} if h is not None else {}))
+    a_true = wl.image(w, seed)
+    V = wl.observations(w, seed, a=a_true)
+    s2 = wl.noise_variance(a_true, w.snr)
+    lo, W = w.window
+    if h is None:
+        rb = np.full(W, 1.0 / W)
+    else:
+        rb, _, _ = oracle.histogram_prior(wl.prior_error_draws(w, seed, 200_000), w.L, lo, W)
+    return w, a_true, V, s2, lo, W, rb
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16", "bf16"])
+@pytest.mark.parametrize("shape", list(SHAPES))
+def test_factored_teacher_forced_step(gpu, prec, shape):
+    import torch
+    from paper_2105_07372_amd import EM
+    w, a_true, V, s2, lo, W, rb = _problem(shape)
+    rng = np.random.default_rng(2)
+    a_t = V.mean(axis=0) + 0.1 * a_true * rng.standard_normal(w.D)
+    rho_t = rb * rng.uniform(0.5, 1.5, W)
+    rho_t /= rho_t.sum()
+    gamma = 0.0 if shape == "full" else 50.0
+    print(f"factored shape={shape} prec={prec} N={w.N} W={W}", flush=True)
+    em = EM(torch.from_numpy(V.astype(np.complex64)).to(gpu), K=w.K, Q=w.Q, L=w.L, sigma2=s2,
+            window=(lo, W), prior=rb, gamma=gamma, precision=prec, factored=True)
+    assert em.info()["kernel"].startswith("pass_fac_kernel"), em.info()
+    em.set_state(a_t, rho_t, 0)
+    offs = oracle.offsets(lo, W)
+    wg, am, mg = em.posterior()
+    wo, _, _ = oracle.estep(V, a_t, rho_t, s2, w.kbar, w.L, offs)
+    ao, mo = oracle.argmax_margin(wo)
+    wg, am, mg = wg.cpu().numpy().astype(np.float64), am.cpu().numpy(), mg.cpu().numpy()
+    assert np.abs(wg - wo).max() <= TOL[prec]["post"]
+    assert np.linalg.norm(wg - wo) / np.linalg.norm(wo) <= TOL[prec]["post"]
+    # argmax bit-exact where the margin exceeds the posterior error bar (single-plane bf16:
+    # twice its 5e-3 bar)
+    sure = mo > (1e-2 if prec == "bf16" else 1e-3)
+    assert int(np.sum(am[sure] != ao[sure])) == 0
+    ll_ref = oracle.loglik(V, a_t, rho_t, s2, w.kbar, w.L, offs)
+    assert abs(em.loglik() - ll_ref) <= TOL[prec]["ll"] * abs(ll_ref)
+    done, ll_step = em.step(1)
+    assert done == 1 and abs(ll_step - ll_ref) <= TOL[prec]["ll"] * abs(ll_ref)
+    it = oracle.em_iteration(V, a_t, rho_t, s2, w.kbar, w.L, offs, rho_bar=rb, gamma=gamma)
+    a1, rho1, _ = em.state()
+    assert np.linalg.norm(a1 - it["a"]) / np.linalg.norm(it["a"]) <= TOL[prec]["a"]
+    assert np.abs(rho1 - it["rho"]).max() <= TOL[prec]["a"]
+    em.close()
+
+
+def test_factored_windowed_trajectory(gpu):
+    """The windowed workload's shape at N = 20000, fp16, 4 iterations from the mean."""
+    import torch
+    from paper_2105_07372_amd import EM
+    w = wl.WORKLOADS["c3"].replace(N=20000)
+    a_true = wl.image(w, 1)
+    V = wl.observations(w, 1, a=a_true)
+    s2 = wl.noise_variance(a_true, w.snr)
+    lo, W = w.window
+    rb, _, _ = oracle.histogram_prior(wl.prior_error_draws(w, 1), w.L, lo, W)
+    a0 = V.astype(np.complex64).astype(np.complex128).mean(axis=0)
+    em = EM(torch.from_numpy(V.astype(np.complex64)).to(gpu), K=w.K, Q=w.Q, L=w.L, sigma2=s2,
+            window=(lo, W), prior=rb, gamma=w.gamma, precision="fp16", a0=a0, factored=True)
+    offs = oracle.offsets(lo, W)
+    a_o, rho_o = a0, rb
+    for t in range(4):
+        ref = oracle.em_iteration(V, a_o, rho_o, s2, w.kbar, w.L, offs, rho_bar=rb, gamma=w.gamma)
+        em.step(1)
+        a, rho, _ = em.state()
+        assert np.linalg.norm(a - ref["a"]) / np.linalg.norm(ref["a"]) <= 3e-4, t
+        assert np.abs(rho - ref["rho"]).max() <= 3e-4, t
+        a_o, rho_o = ref["a"], ref["rho"]
+    em.close()
+
+
+def test_factored_adjoint(gpu):
+    import torch
+    from paper_2105_07372_amd import EM
+    w, a_true, V, s2, lo, W, rb = _problem("win16")
+    rng = np.random.default_rng(4)
+    a = V.mean(axis=0) + 0.2 * a_true
+    eta = np.log(rb + 1e-3) + 0.1 * rng.standard_normal(W)
+    em = EM(torch.from_numpy(V.astype(np.complex64)).to(gpu), K=w.K, Q=w.Q, L=w.L, sigma2=s2,
+            window=(lo, W), prior=rb, precision="fp32", factored=True)
+    a_d = torch.from_numpy(a).to(gpu)
+    e_d = torch.from_numpy(eta).to(gpu)
+    ll = em.loglik_fwd(a_d, s2 * 1.1, e_d)
+    ga = torch.empty_like(a_d)
+    ge = torch.empty_like(e_d)
+    gs = em.loglik_bwd(1.0, ga, ge)
+    r = np.exp(eta - eta.max())
+    r /= r.sum()
+    ll_o, ga_o, gs_o, ge_o = oracle.grad_loglik(V, a, s2 * 1.1, r, w.kbar, w.L,
+                                                oracle.offsets(lo, W))
+    assert abs(ll - ll_o) <= 1e-7 * abs(ll_o)
+    assert np.linalg.norm(ga.cpu().numpy() - ga_o) <= 2e-4 * np.linalg.norm(ga_o)
+    assert abs(gs - gs_o) <= 2e-4 * abs(gs_o)
+    assert np.abs(ge.cpu().numpy() - ge_o).max() <= 2e-4 * max(1.0, np.abs(ge_o).max())
+    em.close()
+
+
+def test_factored_rejects_unsupported_shapes(gpu):
+    import torch
+    from paper_2105_07372_amd import EM, SynchemError
+    V = np.zeros((10, 8 * 6), np.complex64)
+    with pytest.raises(SynchemError) as ei:
+        EM(torch.from_numpy(V).to(gpu), K=8, Q=6, L=12, sigma2=1.0, precision="fp32",
+           factored=True)
+    assert ei.value.status == -6
