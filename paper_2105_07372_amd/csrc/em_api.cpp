@@ -132,11 +132,12 @@ em_status plan(em_ctx *c, size_t lds_max) {
     c->wide = false;
     c->fac = false;
     if (c->flags & EM_FLAG_FACTORED) {
-        int WIDE = 0, KCM = 0;
+        int WIDE = 0, KCM = 0, BM = 0;
         size_t lds = 0;
-        if (c->prec != P_F64 && fac_plan(c->prec, c->D, c->Q, c->K, c->Wp, lds_max, &WIDE, &KCM, &lds)) {
+        if (c->prec != P_F64 &&
+            fac_plan(c->prec, c->D, c->Q, c->K, c->Wp, lds_max, &WIDE, &KCM, &lds, &BM)) {
             c->fac = true;
-            c->BM = kFacBMH;
+            c->BM = BM;
             c->fWIDE = WIDE;
             c->fKCM = KCM;
             c->WM = 0;

@@ -25,7 +25,6 @@ constexpr int kMaxWp = 1024;         // padded window <= 2 * kThreads
 constexpr int kMaxK = 512;
 constexpr int kStatsCap = 1024;
 constexpr int kWideBM = 128;         // rows per tile of the wide-row pass
-constexpr int kFacBMH = 32;          // rows per tile of the factored pass (kFacBM)
 constexpr int kRegTileChunks = 8;    // register-staged tiles: <= 8 x 16 B per thread (64 KiB)
 
 // Bytes of one stored observation row (all planes), Dp reals wide.
@@ -133,7 +132,7 @@ hipError_t launch_pass_wide(int prec, int NTW, int UR, const PassArgs &a, int gr
 hipError_t pass_wide_setup(int prec, int NTW, int UR, size_t lds, int *blocks_per_cu);
 const char *pass_wide_name(int prec, int NTW, int UR);
 bool fac_plan(int prec, int D, int Q, int K, int Wp, size_t lds_max, int *WIDE, int *KCM,
-              size_t *lds);
+              size_t *lds, int *BM);
 hipError_t launch_pass_fac(int prec, int WIDE, int KCM, const PassArgs &a, int grid, size_t lds,
                            hipStream_t s);
 hipError_t pass_fac_setup(int prec, int WIDE, int KCM, size_t lds, int *blocks_per_cu);

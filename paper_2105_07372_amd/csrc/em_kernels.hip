@@ -644,6 +644,58 @@ __device__ __forceinline__ void u_mfma_reg(const float *Cs, int CSW, const float
     }
 }
 
+// Reductions inside each 16-lane DPP row (xor 1, xor 2, half-mirror, mirror): every lane of the
+// row ends with the row's result.  Every lane must be active.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float row16_max(float v) {
+    v = fmaxf(v, dpp_f<0xB1>(v));     // quad_perm [1,0,3,2]
+    v = fmaxf(v, dpp_f<0x4E>(v));     // quad_perm [2,3,0,1]
+    v = fmaxf(v, dpp_f<0x141>(v));    // row_half_mirror
+    return fmaxf(v, dpp_f<0x140>(v)); // row_mirror
+}
+__device__ __forceinline__ float row16_sum(float v) {
+    v += dpp_f<0xB1>(v);
+    v += dpp_f<0x4E>(v);
+    v += dpp_f<0x141>(v);
+    return v + dpp_f<0x140>(v);
+}
+// Reductions over groups of `width` consecutive lanes: 16-lane rows by DPP, wider groups add
+// cross-row shuffles.
+template <typename T>
+__device__ __forceinline__ T rows_max(T v, int width) {
+    if constexpr (sizeof(T) == 4) {
+        if (width >= 16) {
+            v = row16_max(v);
+            for (int o = 16; o < width; o <<= 1) v = fmaxf(v, __shfl_xor(v, o));
+            return v;
+        }
+    }
+    return group_max(v, width);
+}
+template <typename T>
+__device__ __forceinline__ T rows_sum(T v, int width) {
+    if constexpr (sizeof(T) == 4) {
+        if (width >= 16) {
+            v = row16_sum(v);
+            for (int o = 16; o < width; o <<= 1) v += __shfl_xor(v, o);
+            return v;
+        }
+    }
+    return group_sum(v, width);
+}
+template <typename T>
+__device__ __forceinline__ T fast_exp(T x) {
+    if constexpr (sizeof(T) == 4) return __expf(x); else return exp(x);
+}
+template <typename T>
+__device__ __forceinline__ T fast_log(T x) {
+    if constexpr (sizeof(T) == 4) return __logf(x); else return log(x);
+}
+
 // The row-wise part of tile_post: log-sum-exp, posteriors (left in Cs, zero on padding rows and
 // columns), the per-row sums and the posterior queries.
 template <int P, int BM, int DPT>
@@ -663,11 +715,11 @@ __device__ __forceinline__ void tile_rows(const PassArgs &A, int CSW, typename P
         } else {
             CT m = -INFINITY;
             for (int i = sub; i < A.W; i += TPR) m = fmax(m, crow[i]);
-            m = group_max(m, TPR);
+            m = rows_max(m, TPR);
             CT s = 0;
-            for (int i = sub; i < A.W; i += TPR) s += exp(crow[i] - m);
-            s = group_sum(s, TPR);
-            lse = m + log(s);
+            for (int i = sub; i < A.W; i += TPR) s += fast_exp(crow[i] - m);
+            s = rows_sum(s, TPR);
+            lse = m + fast_log(s);
         }
         CT wc = 0;
         CT b1 = -INFINITY, b2 = -INFINITY;
@@ -678,7 +730,7 @@ __device__ __forceinline__ void tile_rows(const PassArgs &A, int CSW, typename P
             const CT l = crow[i];
             CT w = 0;
             if (i < A.W && valid) {
-                w = exp(l - lse);
+                w = fast_exp(l - lse);
                 if (w > (CT)0) {
                     const CT lr = (P == P_F64) ? (CT)A.logrho64[i] : (CT)lr32[i];
                     wc += w * (l - lr);
@@ -696,7 +748,7 @@ __device__ __forceinline__ void tile_rows(const PassArgs &A, int CSW, typename P
             }
             crow[i] = valid ? w : (CT)0;
         }
-        wc = group_sum(wc, TPR);
+        wc = rows_sum(wc, TPR);
         if (query) {
             for (int o = TPR >> 1; o > 0; o >>= 1) {
                 const CT ob1 = __shfl_xor(b1, o, TPR), ob2 = __shfl_xor(b2, o, TPR);
@@ -712,7 +764,7 @@ __device__ __forceinline__ void tile_rows(const PassArgs &A, int CSW, typename P
             if (sub == 0 && valid) {
                 if (A.argmax) A.argmax[qrow] = i1;
                 if (A.margin) {
-                    const CT w1 = exp(b1 - lse), w2 = (A.W > 1) ? exp(b2 - lse) : (CT)0;
+                    const CT w1 = fast_exp(b1 - lse), w2 = (A.W > 1) ? fast_exp(b2 - lse) : (CT)0;
                     A.margin[qrow] = (float)(w1 - w2);
                 }
             }
@@ -1008,14 +1060,8 @@ __host__ __device__ constexpr int bytes_per_real() {
     return P == P_BF16X3 ? 4 : (P == P_F32 ? 4 : 2);
 }
 
-// Wave-wide reductions with DPP butterflies inside each 16-lane row (xor 1, xor 2, half-mirror,
-// mirror), then the four row results combined in a fixed order through readlane.  Every lane
-// must be active.
-template <int CTRL>
-__device__ __forceinline__ float dpp_f(float v) {
-    return __builtin_bit_cast(
-        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
-}
+// Wave-wide reductions: the 16-lane row reductions (row16_*), then the four row results
+// combined in a fixed order through readlane.  Every lane must be active.
 __device__ __forceinline__ float rl_f(float v, int lane) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
 }
@@ -1720,7 +1766,7 @@ __global__ __launch_bounds__(kThreads) void pass_wide_kernel(PassArgs A) {
 // contraction (a rotation is one phase per angular frequency, §I eq. (3)):
 //   Re <v_j, R_{o_i} a> = Re sum_k c_jk exp(-i k theta_i),   c_jk = sum_q conj(v_jkq) a_kq.
 // Per row this costs 4D + 4KW flops instead of 4DW, no template exists, and the pass is a stream
-// over the rows.  Each wave owns kFacRPW rows of a tile of kFacBM rows and holds them in
+// over the rows.  Each wave owns fac_rpw rows of a tile of 8 fac_rpw rows and holds them in
 // registers (lane l: entries 8l .. 8l+7, so D = 512; Q/8 lanes share an angular frequency),
 // while the next tile's rows load.  c goes to LDS; C = [Re c | Im c] . [cos; sin] and
 // U = w [Re E | Im E] are FP32 matrix-core products against the phase table (fragments in
@@ -1728,23 +1774,25 @@ __global__ __launch_bounds__(kThreads) void pass_wide_kernel(PassArgs A) {
 // the M-step from the rows in registers, the eight waves' partial sums added in wave order into
 // per-entry FP64 accumulators.
 
-constexpr int kFacRPW = 4;                    // rows per wave per tile
-constexpr int kFacBM = 8 * kFacRPW;           // rows per tile
-static_assert(kFacBM == kFacBMH, "host and device tile sizes");
+// rows per wave per tile: 2 for the 16-word row formats (FP32, bf16x3), 4 for one 16-bit plane
+__host__ __device__ constexpr int fac_rpw(int prec) {
+    return (prec == P_F32 || prec == P_BF16X3) ? 2 : 4;
+}
 constexpr int kFacEPL = 8;                    // entries per lane: D = 64 kFacEPL
+constexpr int kFacFlush = 4;                  // tiles summed in FP32 before the FP64 flush
 
 struct FacLds {
     int CBW, CSW, off_cs, off_u, off_sw, off_f, off_lr, off_a, total;
 };
-__host__ __device__ inline FacLds fac_lds(int K, int D, int Wp, int KCM) {
+__host__ __device__ inline FacLds fac_lds(int K, int D, int Wp, int KCM, int BM) {
     FacLds l;
     l.CBW = 4 * KCM + 4;                       // [Re c | Im c | 0 ..], conflict-free A reads
     l.CSW = (Wp > 64 ? Wp : 64) + 4;           // columns past Wp stay zero (register U path)
-    l.off_cs = align_up(kFacBM * l.CBW * 4, 16);
-    l.off_u = align_up(l.off_cs + kFacBM * l.CSW * 4, 16);
-    l.off_sw = align_up(l.off_u + kFacBM * K * 8, 16);
+    l.off_cs = align_up(BM * l.CBW * 4, 16);
+    l.off_u = align_up(l.off_cs + BM * l.CSW * 4, 16);
+    l.off_sw = align_up(l.off_u + BM * K * 8, 16);
     l.off_f = align_up(l.off_sw + 8 * D * 8, 16);
-    l.off_lr = l.off_f + 2 * kFacBM * 4;
+    l.off_lr = l.off_f + 2 * BM * 4;
     l.off_a = align_up(l.off_lr + Wp * 4, 16);
     l.total = l.off_a + D * 8;
     return l;
@@ -1798,7 +1846,7 @@ struct FacRow {
 template <int P, int WIDE, int KCM>
 __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
     static_assert(P != P_F64, "matrix-core precisions");
-    constexpr int BM = kFacBM, RPW = kFacRPW, EPL = kFacEPL, DPT = 1;   // D = 512 = threads
+    constexpr int RPW = fac_rpw(P), BM = 8 * RPW, EPL = kFacEPL, DPT = 1;   // D = 512 = threads
     if ((A.flags & PF_CHECK_STOP) && *A.stopped) return;
 
     extern __shared__ __align__(16) uint8_t smem[];
@@ -1806,7 +1854,7 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int g = lane >> 4, c = lane & 15;
     const int K = A.K, D = A.D, Wp = A.Wp, NT = Wp / 16;
-    const FacLds LY = fac_lds(K, D, Wp, KCM);
+    const FacLds LY = fac_lds(K, D, Wp, KCM, BM);
     float *cb = (float *)smem;
     float *Cs = (float *)(smem + LY.off_cs);
     float2 *Us = (float2 *)(smem + LY.off_u);
@@ -1827,7 +1875,7 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
     // C product: wave w computes rows 16 (w >> 2) .. of window tile (w & 3) (Wp <= 64); its B
     // fragments E2[16 n + c][4 kk + g] (zero past 2K)
     float cfr[KCM];
-    const int cm = wave >> 2, cn = wave & 3;
+    const int cm = wave >> 2, cn = wave & 3;       // (16-row tiles: waves 0-3 only)
     if constexpr (!WIDE) {
 #pragma unroll
         for (int kk = 0; kk < KCM; ++kk) {
@@ -1859,6 +1907,33 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
             vn[r].load(A.V + row * A.rowbytes, A.Dp, lane);
             rsn[r] = A.rowscale ? A.rowscale[row] : 1.0f;
         }
+    };
+    float sr[EPL], si[EPL];                   // this lane's M-step partials (FP32)
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) sr[e] = si[e] = 0.f;
+    int nacc = 0;
+    auto flush = [&]() {
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) Sw[wave * D + d0 + e] = make_float2(sr[e], si[e]);
+        __syncthreads();
+#pragma unroll
+        for (int cc = 0; cc < DPT; ++cc) {
+            const int d = tid + cc * kThreads;
+            if (d < D) {
+                float2 s = Sw[d];
+#pragma unroll
+                for (int w = 1; w < 8; ++w) {
+                    const float2 t = Sw[w * D + d];
+                    s.x += t.x;
+                    s.y += t.y;
+                }
+                acc.S[cc].x += (double)s.x;
+                acc.S[cc].y += (double)s.y;
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) sr[e] = si[e] = 0.f;
+        nacc = 0;
     };
     int64_t tile = blockIdx.x;
     if (tile < ntiles) load_tile(tile);
@@ -1905,6 +1980,7 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
 
         // ---- C = [Re c | Im c] . E2^T on FP32 matrix cores -> l' = coef C / s_j + log rho
         if constexpr (!WIDE) {
+          if (16 * cm < BM) {
             f32x4 cacc = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int kk = 0; kk < KCM; ++kk) {
@@ -1917,9 +1993,11 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
                 const int row = 16 * cm + 4 * g + q;
                 Cs[row * LY.CSW + col] = cn < NT ? cacc[q] * rowf[row] + lrs[col] : 0.f;
             }
+          }
         } else {
-            for (int p = wave; p < 2 * NT; p += 8) {
-                const int m = p & 1, n = p >> 1;
+            constexpr int MT = BM / 16;
+            for (int p = wave; p < MT * NT; p += 8) {
+                const int m = p % MT, n = p / MT;
                 f32x4 cacc = (f32x4){0.f, 0.f, 0.f, 0.f};
                 const float *eb = A.E2 + (int64_t)(16 * n + c) * 2 * K;
 #pragma unroll
@@ -1949,10 +2027,8 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
         else
             u_mfma<BM>(Cs, LY.CSW, A.E2, Wp, K, rowu, Us);
         __syncthreads();
-        // M-step from the rows in registers: this lane's entries over this wave's rows
-        float sr[EPL], si[EPL];
-#pragma unroll
-        for (int e = 0; e < EPL; ++e) sr[e] = si[e] = 0.f;
+        // M-step from the rows in registers: this lane's entries over this wave's rows, summed
+        // in FP32 over kFacFlush tiles, then the eight waves' partials in wave order into FP64
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
             const int j = RPW * wave + r;
@@ -1964,24 +2040,7 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
                 si[e] += u.x * v.y + u.y * v.x;
             }
         }
-#pragma unroll
-        for (int e = 0; e < EPL; ++e) Sw[wave * D + d0 + e] = make_float2(sr[e], si[e]);
-        __syncthreads();
-#pragma unroll
-        for (int cc = 0; cc < DPT; ++cc) {
-            const int d = tid + cc * kThreads;
-            if (d < D) {
-                float2 s = Sw[d];
-#pragma unroll
-                for (int w = 1; w < 8; ++w) {
-                    const float2 t = Sw[w * D + d];
-                    s.x += t.x;
-                    s.y += t.y;
-                }
-                acc.S[cc].x += (double)s.x;
-                acc.S[cc].y += (double)s.y;
-            }
-        }
+        if (++nacc == kFacFlush || tile + gridDim.x >= ntiles) flush();
     }
     __syncthreads();
     if (A.partials) write_partials(A, acc, smem);
@@ -2442,18 +2501,19 @@ static pass_fn find_fac(int prec, int WIDE, int KCM) {
 }
 
 bool fac_plan(int prec, int D, int Q, int K, int Wp, size_t lds_max, int *WIDE, int *KCM,
-              size_t *lds) {
+              size_t *lds, int *BM) {
     if (D != 64 * kFacEPL || Q % kFacEPL != 0) return false;
     const int lpk = Q / kFacEPL;
     if (lpk & (lpk - 1)) return false;                       // lanes per frequency: 2^n
     const int kcm = 2 * K <= 64 ? 16 : (2 * K <= 128 ? 32 : 0);
     const int wide = Wp > 64 ? 1 : 0;
     if (!kcm || !find_fac(prec, wide, kcm)) return false;
-    const size_t b = (size_t)fac_lds(K, D, Wp, kcm).total;
+    const size_t b = (size_t)fac_lds(K, D, Wp, kcm, 8 * fac_rpw(prec)).total;
     if (b > lds_max) return false;
     *WIDE = wide;
     *KCM = kcm;
     *lds = b;
+    *BM = 8 * fac_rpw(prec);
     return true;
 }
 
@@ -2477,7 +2537,8 @@ hipError_t pass_fac_setup(int prec, int WIDE, int KCM, size_t lds, int *blocks_p
 
 const char *pass_fac_name(int prec, int WIDE, int KCM) {
     static char buf[64];
-    snprintf(buf, sizeof buf, "pass_fac_kernel<%s,BM=%d,%s,KC=%d>", kPrecName[prec], kFacBM,
+    snprintf(buf, sizeof buf, "pass_fac_kernel<%s,BM=%d,%s,KC=%d>", kPrecName[prec],
+             8 * fac_rpw(prec),
              WIDE ? "L2" : "reg", KCM);
     return buf;
 }
