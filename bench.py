@@ -7,7 +7,8 @@ correlations (observations and template each bf16 hi+lo, three products, FP32 ac
 One step is one EM iteration over all N observations (E-step correlations, prior-weighted
 posterior, fused M-step accumulation, FP64 finalize, next template).  The same run times the
 plain full-search FP32 EM (all 360 rotations, uniform prior) on the same observations, the fp16
-windowed variant, and the FP64 CPU oracle on the host cores.
+windowed variant, the factored E-step (per-frequency sums, an exact rewrite of the correlation:
+windowed FP32 / fp16 and full search FP32), and the FP64 CPU oracle on the host cores.
 
 Prints one JSON line.  --gpus N with N > 1 is refused: this build runs on one GPU.
 """
@@ -159,13 +160,19 @@ def main():
     log(f"bench: windowed {iters_s:.1f} it/s, pass {pass_ms * 1e3:.1f} us")
 
     variants = {}
-    for prec in ("fp16",) if args.precision != "fp16" else ():
+    runs = [(f"windowed_{p}", dict(precision=p)) for p in ("fp16",) if args.precision != "fp16"]
+    # the factored E-step (per-frequency sums, an exact rewrite of the correlation)
+    runs += [(f"windowed_factored_{p}", dict(precision=p, factored=True)) for p in ("fp32", "fp16")]
+    for name, kw in runs:
         e2 = EM(obs, K=w.K, Q=w.Q, L=w.L, sigma2=s2, window=(lo, W), prior=rb, gamma=w.gamma,
-                precision=prec, timing=True)
+                timing=True, **kw)
         d2, p2, _ = time_em(e2, args.steps, args.warmup, (a0, rb, 0))
-        variants[f"windowed_{prec}"] = {"iter_per_s": args.steps / d2,
-                                        "pass_us": p2 * 1e3, "kernel": e2.info()["kernel"]}
+        variants[name] = {"iter_per_s": args.steps / d2, "pass_us": p2 * 1e3,
+                          "kernel": e2.info()["kernel"],
+                          "hbm_frac": float(w.N) * e2.info()["bytes_per_row"] / (p2 * 1e-3) / 1e9
+                          / HBM_PEAK_GBS}
         e2.close()
+        log(f"bench: {name} {variants[name]['iter_per_s']:.1f} it/s")
 
     baseline = None
     if not args.no_baseline:
@@ -181,6 +188,12 @@ def main():
                     "pass_us": pf * 1e3, "kernel": ef.info()["kernel"]}
         ef.close()
         log(f"bench: full search fp32 {baseline['iter_per_s']:.1f} it/s")
+        ef = EM(obs, K=w.K, Q=w.Q, L=w.L, sigma2=s2, precision="fp32", timing=True,
+                a0=wl.random_init(w2, 0), factored=True)
+        df, pf, _ = time_em(ef, nsteps, 2, (wl.random_init(w2, 0), np.full(w.L, 1.0 / w.L), 0))
+        variants["full_search_factored_fp32"] = {"iter_per_s": nsteps / df, "pass_us": pf * 1e3,
+                                                 "kernel": ef.info()["kernel"]}
+        ef.close()
 
     cpu = None
     acc = None

@@ -553,11 +553,11 @@ struct TileLoader {
 
 // U (BM x 2K, as complex [BM][K]) = w (BM x Wp, the posterior tile in LDS) . [Re E | Im E]
 // (Wp x 2K) on FP32 matrix cores (16x16x4), each row scaled by rowu; wave w computes the 16-column
-// tiles w, w + 8, ... of U for all rows.  The B fragments stream from L2 through a 4-deep ring.
-template <int BM>
+// tiles w, w + 8, ... of U for all rows.  The B fragments stream from L2 through a RING-deep register ring.
+template <int BM, int RING = 4>
 __device__ __forceinline__ void u_mfma(const float *Cs, int CSW, const float *E2, int Wp, int K,
                                        const float *rowu, float2 *Us) {
-    constexpr int MS = BM / 16, RING = 4;
+    constexpr int MS = BM / 16;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, rl = lane & 15;
     const int NTU = (2 * K + 15) / 16, KG = Wp / 4;
     for (int nt = wave; nt < NTU; nt += kThreads / 64) {
@@ -1791,7 +1791,7 @@ __host__ __device__ inline FacLds fac_lds(int K, int D, int Wp, int KCM, int BM)
     l.off_cs = align_up(BM * l.CBW * 4, 16);
     l.off_u = align_up(l.off_cs + BM * l.CSW * 4, 16);
     l.off_sw = align_up(l.off_u + BM * K * 8, 16);
-    l.off_f = align_up(l.off_sw + 8 * D * 8, 16);
+    l.off_f = align_up(l.off_sw + 8 * (9 * D / 8) * 8, 16);
     l.off_lr = l.off_f + 2 * BM * 4;
     l.off_a = align_up(l.off_lr + Wp * 4, 16);
     l.total = l.off_a + D * 8;
@@ -1862,10 +1862,12 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
     float *rowf = (float *)(smem + LY.off_f);
     float *rowu = rowf + BM;
     float *lrs = (float *)(smem + LY.off_lr);
-    float2 *as = (float2 *)(smem + LY.off_a);                 // a (FP32), D entries
+    // a (FP32) stored lane-major: entry e of lane l at [e][l], so the lanes' reads are
+    // conflict-free
+    float2 *as = (float2 *)(smem + LY.off_a);
     for (int i = tid; i < Wp; i += kThreads) lrs[i] = A.logrho32[i];
     for (int d = tid; d < D; d += kThreads)
-        as[d] = make_float2((float)A.a[2 * d], (float)A.a[2 * d + 1]);
+        as[(d % EPL) * 64 + d / EPL] = make_float2((float)A.a[2 * d], (float)A.a[2 * d + 1]);
 
     // this lane's entries and their coefficients a (FP32), its angular frequency and lane group
     const int d0 = EPL * lane;
@@ -1913,17 +1915,21 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
     for (int e = 0; e < EPL; ++e) sr[e] = si[e] = 0.f;
     int nacc = 0;
     auto flush = [&]() {
+        // wave w's partials at [w][9 (d / 8) + d % 8] (padded: the lanes' writes spread over
+        // the banks)
+        const int SWS = 9 * D / 8;
 #pragma unroll
-        for (int e = 0; e < EPL; ++e) Sw[wave * D + d0 + e] = make_float2(sr[e], si[e]);
+        for (int e = 0; e < EPL; ++e) Sw[wave * SWS + 9 * lane + e] = make_float2(sr[e], si[e]);
         __syncthreads();
 #pragma unroll
         for (int cc = 0; cc < DPT; ++cc) {
             const int d = tid + cc * kThreads;
             if (d < D) {
-                float2 s = Sw[d];
+                const int o = 9 * (d >> 3) + (d & 7);
+                float2 s = Sw[o];
 #pragma unroll
                 for (int w = 1; w < 8; ++w) {
-                    const float2 t = Sw[w * D + d];
+                    const float2 t = Sw[w * SWS + o];
                     s.x += t.x;
                     s.y += t.y;
                 }
@@ -1957,7 +1963,7 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
 #pragma unroll
             for (int e = 0; e < EPL; ++e) {
                 const float2 v = vc[r].entry(e);
-                const float2 av = as[d0 + e];
+                const float2 av = as[e * 64 + lane];
                 cr += v.x * av.x + v.y * av.y;            // Re conj(v) a
                 ci += v.x * av.y - v.y * av.x;            // Im conj(v) a
             }
