@@ -228,11 +228,12 @@ def test_nonfinite_observations_rejected(gpu):
     assert ei.value.status == -5
 
 
-@pytest.mark.parametrize("prec", ["bf16x3", "fp16"])
-def test_full_size_windowed_step(gpu, prec):
-    """The windowed workload at full size (N=1e5, D=512, L=360, W=49, gamma=100): one EM step
-    from a_0 = mean v, the estimate and rho against the oracle on all rows, the posteriors on
-    sampled row blocks."""
+@pytest.mark.parametrize("prec,factored", [("bf16x3", False), ("fp16", False), ("fp32", True),
+                                           ("fp16", True)])
+def test_full_size_windowed_step(gpu, prec, factored):
+    """The windowed workload at full size (N=1e5, D=512, L=360, W=49, gamma=100), with the
+    correlation pass and with the factored pass: one EM step from a_0 = mean v, the estimate and
+    rho against the oracle on all rows, the posteriors on sampled row blocks."""
     from paper_2105_07372_amd import EM
     w = wl.WORKLOADS["c3"]
     a_true = wl.image(w, 0)
@@ -241,7 +242,7 @@ def test_full_size_windowed_step(gpu, prec):
     lo, W = w.window
     rb, _, _ = oracle.histogram_prior(wl.prior_error_draws(w, 0), w.L, lo, W)
     em = EM(_obs(V, prec, gpu), K=w.K, Q=w.Q, L=w.L, sigma2=s2, window=(lo, W), prior=rb,
-            gamma=w.gamma, precision=prec)
+            gamma=w.gamma, precision=prec, factored=factored)
     a0 = V.astype(np.complex64).astype(np.complex128).mean(axis=0)   # the GPU gets complex64
     a_g0 = em.state()[0]
     assert np.linalg.norm(a_g0 - a0) <= 1e-12 * np.linalg.norm(a0)
@@ -257,15 +258,18 @@ def test_full_size_windowed_step(gpu, prec):
     em.close()
 
 
-def test_full_size_full_search_step(gpu):
-    """The plain full-search workload at full size (N=1e5, D=512, L=360, FP32): one step."""
+@pytest.mark.parametrize("factored", [False, True])
+def test_full_size_full_search_step(gpu, factored):
+    """The plain full-search workload at full size (N=1e5, D=512, L=360, FP32): one step, with
+    the correlation pass and with the factored pass."""
     from paper_2105_07372_amd import EM
     w = wl.WORKLOADS["c2"]
     a_true = wl.image(w, 0)
     V = wl.observations(w, 0, a=a_true)
     s2 = wl.noise_variance(a_true, w.snr)
     a0 = wl.random_init(w, 0)
-    em = EM(_obs(V, "fp32", gpu), K=w.K, Q=w.Q, L=w.L, sigma2=s2, precision="fp32", a0=a0)
+    em = EM(_obs(V, "fp32", gpu), K=w.K, Q=w.Q, L=w.L, sigma2=s2, precision="fp32", a0=a0,
+            factored=factored)
     rho = np.full(w.L, 1.0 / w.L)
     _compare_posteriors(em, V, a0, rho, s2, w, 0, w.L, "fp32", row0=50_000, nrows=2000)
     em.step(1)
