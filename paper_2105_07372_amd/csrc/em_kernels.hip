@@ -42,6 +42,16 @@ __device__ __forceinline__ T group_sum(T v, int width) {
     return v;
 }
 
+// Workgroup barrier for LDS hand-offs only: waits for this wave's LDS accesses, not for its
+// vector-memory loads (a __syncthreads() would also drain the copies and prefetch loads still in
+// flight, which every pass keeps in flight across its tile phases).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_s_waitcnt(15 | (7 << 4) | (0 << 8) | (3 << 14));
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
 // Deterministic block sum of one double per thread (fixed tree order). All threads get the sum.
 __device__ double block_sum_d(double v, double *sh, int n) {
     const int t = threadIdx.x;
@@ -819,7 +829,7 @@ __device__ __forceinline__ void tile_post(const PassArgs &A, const PassLds &LY, 
     const int tid = threadIdx.x;
     tile_rows<P, BM, DPT>(A, LY.CSW, Cs, lr32, r0, rows, acc);
     if (!(A.flags & PF_ACC_M)) return;
-    __syncthreads();
+    lds_barrier();
     tile_wsum<P, DPT>(A, LY.CSW, Cs, rows, acc);
     // U_jk = sum_i w_ji exp(+i k theta_i), scaled back to the rows' storage scale
     if constexpr (P == P_F64) {
@@ -839,7 +849,7 @@ __device__ __forceinline__ void tile_post(const PassArgs &A, const PassLds &LY, 
     } else {
         u_mfma<BM>(Cs, LY.CSW, A.E2, A.Wp, A.K, rowu, Us);
     }
-    __syncthreads();
+    lds_barrier();
     // M-step: S_d += sum_j U_{j, kbar_d} v_jd (complex product, no conjugate)
 #pragma unroll
     for (int c = 0; c < DPT; ++c) {
@@ -972,7 +982,7 @@ __global__ __launch_bounds__(kThreads) void pass_kernel(PassArgs A) {
             if (tile + gridDim.x < ntiles)
                 dma_issue_tile(A, tile + gridDim.x, BM, smem + (buf ? 0 : LY.off_v1), LY.RS);
         } else {
-            __syncthreads();                                // previous tile fully consumed
+            lds_barrier();                                // previous tile fully consumed
             ld.store(Vs, LY.RS, BM, A.rowbytes);
         }
         for (int j = tid; j < BM; j += kThreads) {
@@ -985,7 +995,7 @@ __global__ __launch_bounds__(kThreads) void pass_kernel(PassArgs A) {
             rowf[j] = f;
             rowu[j] = u;
         }
-        __syncthreads();
+        lds_barrier();
         if constexpr (!LD)
             if (tile + gridDim.x < ntiles) ld.issue(A, tile + gridDim.x, BM);
 
@@ -1022,7 +1032,7 @@ __global__ __launch_bounds__(kThreads) void pass_kernel(PassArgs A) {
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
         const float nore[1] = {0.f};
         tile_post<P, BM, kMaxDPerThread, 0>(A, LY, Vs, Cs, Us, rowu, lrs, r0, rows, acc, nore,
                                             false, 0);
@@ -1072,6 +1082,35 @@ __device__ __forceinline__ float wave_max_f(float v) {
     v = fmaxf(v, dpp_f<0x140>(v));    // row_mirror
     return fmaxf(fmaxf(rl_f(v, 0), rl_f(v, 16)), fmaxf(rl_f(v, 32), rl_f(v, 48)));
 }
+// H independent wave reductions, their steps interleaved.
+template <int H>
+__device__ __forceinline__ void wave_max_fn(float (&v)[H]) {
+#pragma unroll
+    for (int h = 0; h < H; ++h) v[h] = fmaxf(v[h], dpp_f<0xB1>(v[h]));
+#pragma unroll
+    for (int h = 0; h < H; ++h) v[h] = fmaxf(v[h], dpp_f<0x4E>(v[h]));
+#pragma unroll
+    for (int h = 0; h < H; ++h) v[h] = fmaxf(v[h], dpp_f<0x141>(v[h]));
+#pragma unroll
+    for (int h = 0; h < H; ++h) v[h] = fmaxf(v[h], dpp_f<0x140>(v[h]));
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+        v[h] = fmaxf(fmaxf(rl_f(v[h], 0), rl_f(v[h], 16)), fmaxf(rl_f(v[h], 32), rl_f(v[h], 48)));
+}
+template <int H>
+__device__ __forceinline__ void wave_sum_fn(float (&v)[H]) {
+#pragma unroll
+    for (int h = 0; h < H; ++h) v[h] += dpp_f<0xB1>(v[h]);
+#pragma unroll
+    for (int h = 0; h < H; ++h) v[h] += dpp_f<0x4E>(v[h]);
+#pragma unroll
+    for (int h = 0; h < H; ++h) v[h] += dpp_f<0x141>(v[h]);
+#pragma unroll
+    for (int h = 0; h < H; ++h) v[h] += dpp_f<0x140>(v[h]);
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+        v[h] = (rl_f(v[h], 0) + rl_f(v[h], 16)) + (rl_f(v[h], 32) + rl_f(v[h], 48));
+}
 __device__ __forceinline__ float wave_sum_f(float v) {
     v += dpp_f<0xB1>(v);
     v += dpp_f<0x4E>(v);
@@ -1096,45 +1135,63 @@ __device__ __forceinline__ void ks_post(const PassArgs &A, const KsLds &LY, cons
     const int col = lane, nt = lane >> 4;
     const bool cval = col < A.W;
     const float lr = col < A.Wp ? lrs[col] : -INFINITY;
-    float wsum = 0.f;
+    // this wave's H = BM / 8 rows (wave, wave + 8, ...), their reductions interleaved step by step
+    constexpr int H = BM / 8;
+    float l[H], lse[H], w[H], wc[H];
+    bool rv[H];
 #pragma unroll
-    for (int h = 0; h < BM / 8; ++h) {
+    for (int h = 0; h < H; ++h) {
         const int r = wave + 8 * h;
-        const bool rval = r < rows;
+        rv[h] = r < rows;
         const int m = r >> 4, rr = r & 15;
         const int ln = (rr >> 2) * 16 + (col & 15), q = rr & 3;
-        float l = -INFINITY;
-        if (cval && rval) {
+        l[h] = -INFINITY;
+        if (cval && rv[h]) {
             float v = red[((0 * MS + m) * NT + nt) * 64 + ln][q];
             v += red[((1 * MS + m) * NT + nt) * 64 + ln][q];
             v += red[((2 * MS + m) * NT + nt) * 64 + ln][q];
             v += red[((3 * MS + m) * NT + nt) * 64 + ln][q];
-            l = v * rowf[r] + lr;
+            l[h] = v * rowf[r] + lr;
         }
-        float lse;
-        if (A.flags & PF_LOAD_LSE) {
-            lse = rval ? (float)A.lse[r0 + r] : 0.f;
-        } else {
-            const float mx = wave_max_f(l);
-            const float s = wave_sum_f((cval && rval) ? __expf(l - mx) : 0.f);
-            lse = mx + __logf(s);
-        }
-        const float w = (cval && rval) ? __expf(l - lse) : 0.f;
-        const float wc = wave_sum_f(w > 0.f ? w * (l - lr) : 0.f);
-        if (col < A.Wp) Cs[r * LY.CSW + col] = w;
-        wsum += w;
-        if (lane == 0 && rval) {
-            acc.lse += (double)lse;
-            acc.wc += (double)wc;
+    }
+    if (A.flags & PF_LOAD_LSE) {
+#pragma unroll
+        for (int h = 0; h < H; ++h) lse[h] = rv[h] ? (float)A.lse[r0 + wave + 8 * h] : 0.f;
+    } else {
+        float mx[H], sx[H];
+#pragma unroll
+        for (int h = 0; h < H; ++h) mx[h] = l[h];
+        wave_max_fn<H>(mx);
+#pragma unroll
+        for (int h = 0; h < H; ++h) sx[h] = (cval && rv[h]) ? __expf(l[h] - mx[h]) : 0.f;
+        wave_sum_fn<H>(sx);
+#pragma unroll
+        for (int h = 0; h < H; ++h) lse[h] = mx[h] + __logf(sx[h]);
+    }
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        w[h] = (cval && rv[h]) ? __expf(l[h] - lse[h]) : 0.f;
+        wc[h] = w[h] > 0.f ? w[h] * (l[h] - lr) : 0.f;
+    }
+    wave_sum_fn<H>(wc);
+    float wsum = 0.f;
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        const int r = wave + 8 * h;
+        if (col < A.Wp) Cs[r * LY.CSW + col] = w[h];
+        wsum += w[h];
+        if (lane == 0 && rv[h]) {
+            acc.lse += (double)lse[h];
+            acc.wc += (double)wc[h];
             acc.rows += 1.0;
-            if (A.flags & PF_STORE_LSE) A.lse[r0 + r] = (double)lse;
+            if (A.flags & PF_STORE_LSE) A.lse[r0 + r] = (double)lse[h];
         }
     }
     accWl += (double)wsum;
     if (!(A.flags & PF_ACC_M)) return;
-    __syncthreads();
+    lds_barrier();
     u_mfma_reg<BM, KG>(Cs, LY.CSW, ereg, A.K, rowu, Us, uact, ucol);
-    __syncthreads();
+    lds_barrier();
     // M-step: S_d += sum_j U_{j, kbar_d} v_jd, all BM rows unconditionally (rows past the
     // tile's end are masked by a select, so stale LDS contents cannot leak in)
 #pragma unroll
@@ -1328,7 +1385,7 @@ __global__ __launch_bounds__(kThreads) void pass_ks_kernel(PassArgs A) {
                 for (int nt = 0; nt < NT; ++nt)
                     red[(((wave - 4) * MS + m) * NT + nt) * 64 + lane] = c4[m][nt];
         }
-        __syncthreads();
+        lds_barrier();
         if (wave < 4) {
 #pragma unroll
             for (int m = 0; m < MS; ++m)
@@ -1338,7 +1395,7 @@ __global__ __launch_bounds__(kThreads) void pass_ks_kernel(PassArgs A) {
                     *slot = c4[m][nt] + *slot;
                 }
         }
-        __syncthreads();
+        lds_barrier();
         if constexpr (!query) {
             ks_post<P, BM, NT, DPT, KG>(A, LY, Vs, red, Cs, Us, rowf, rowu, lrs, r0, rows, acc,
                                          accWl, ereg, uact, ucol);
@@ -1354,7 +1411,7 @@ __global__ __launch_bounds__(kThreads) void pass_ks_kernel(PassArgs A) {
             v += red[((3 * MS + m) * NT + nt) * 64 + ln][q];
             Cs[row * LY.CSW + col] = v * rowf[row] + lrs[col];
         }
-        __syncthreads();
+        lds_barrier();
         if constexpr (query)
             tile_post<P, BM, DPT, KG>(A, PL, Vs, Cs, Us, rowu, lrs, r0, rows, acc, ereg, uact,
                                       ucol);
@@ -1421,14 +1478,6 @@ __device__ __forceinline__ void wait_vm() {
     asm volatile("" ::: "memory");
 }
 
-// Workgroup barrier for LDS hand-offs only: waits for this wave's LDS accesses, not for its
-// vector-memory loads (a __syncthreads() would also drain the copies still in flight).
-__device__ __forceinline__ void lds_barrier() {
-    __builtin_amdgcn_s_waitcnt(15 | (7 << 4) | (0 << 8) | (3 << 14));
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");
-}
 
 typedef __amdgpu_buffer_rsrc_t rsrc_t;
 __device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint32_t bytes) {
@@ -1920,7 +1969,7 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
         const int SWS = 9 * D / 8;
 #pragma unroll
         for (int e = 0; e < EPL; ++e) Sw[wave * SWS + 9 * lane + e] = make_float2(sr[e], si[e]);
-        __syncthreads();
+        lds_barrier();
 #pragma unroll
         for (int cc = 0; cc < DPT; ++cc) {
             const int d = tid + cc * kThreads;
@@ -1982,7 +2031,7 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
                 rowu[j] = u;
             }
         }
-        __syncthreads();
+        lds_barrier();
 
         // ---- C = [Re c | Im c] . E2^T on FP32 matrix cores -> l' = coef C / s_j + log rho
         if constexpr (!WIDE) {
@@ -2021,18 +2070,18 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
 
         // ---- a4 + a5
         tile_rows<P, BM, DPT>(A, LY.CSW, Cs, lrs, r0, rows, acc);
         if (!(A.flags & PF_ACC_M)) continue;
-        __syncthreads();
+        lds_barrier();
         tile_wsum<P, DPT>(A, LY.CSW, Cs, rows, acc);
         if constexpr (!WIDE)
             u_wide_reg<BM, 16>(Cs, LY.CSW, ereg, K, rowu, Us, ucol);
         else
             u_mfma<BM>(Cs, LY.CSW, A.E2, Wp, K, rowu, Us);
-        __syncthreads();
+        lds_barrier();
         // M-step from the rows in registers: this lane's entries over this wave's rows, summed
         // in FP32 over kFacFlush tiles, then the eight waves' partials in wave order into FP64
 #pragma unroll
