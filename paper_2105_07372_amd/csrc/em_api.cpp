@@ -654,8 +654,7 @@ em_status em_step(em_ctx *c, int32_t n_iter, double tol, int32_t *iters_done, do
         em_status st = run_pass(c, flags, 0, c->N, c->a, c->Thi, c->Tlo, c->tscale, c->logrho32,
                                 c->logrho64, coef, nullptr, nullptr, nullptr, true, true);
         if (st != EM_OK) return st;
-        HIPCHK(c, launch_reduce(c->partials, c->grid, c->ncols, c->red, c->stream));
-        HIPCHK(c, launch_finalize(F, c->stream));
+        HIPCHK(c, launch_reduce_finalize(F, c->partials, c->grid, c->ncols, c->red, c->stream));
         if (!c->ks && !c->fac)   // these passes use a_t itself
             if ((st = run_template(c, c->a, c->Thi, c->Tlo, c->tscale, true)) != EM_OK) return st;
     }
@@ -677,9 +676,8 @@ em_status em_loglik(em_ctx *c, double *ll) {
     em_status st = run_pass(c, 0, 0, c->N, c->a, c->Thi, c->Tlo, c->tscale, c->logrho32, c->logrho64,
                             2.0 / c->sigma2, nullptr, nullptr, nullptr, true, false);
     if (st != EM_OK) return st;
-    HIPCHK(c, launch_reduce(c->partials, c->grid, c->ncols, c->red, c->stream));
     FinArgs F = fin_base(c, FIN_LL);
-    HIPCHK(c, launch_finalize(F, c->stream));
+    HIPCHK(c, launch_reduce_finalize(F, c->partials, c->grid, c->ncols, c->red, c->stream));
     HIPCHK(c, hipMemcpyAsync(ll, c->scal, 8, hipMemcpyDeviceToHost, c->stream));
     return sync(c);
 }
@@ -749,12 +747,11 @@ em_status em_loglik_fwd(em_ctx *c, const double *a_dev, double sigma2, const dou
     st = run_pass(c, PF_STORE_LSE, 0, c->N, c->aE, c->ThiE, c->TloE, c->tscaleE, c->logrho32E,
                   c->logrho64E, 2.0 / sigma2, nullptr, nullptr, nullptr, true, false);
     if (st != EM_OK) return st;
-    HIPCHK(c, launch_reduce(c->partials, c->grid, c->ncols, c->red, c->stream));
     FinArgs F = fin_base(c, FIN_LL);
     F.sigma2 = sigma2;
     F.a_in = c->aE;
     F.rho_in = c->rhoE;
-    HIPCHK(c, launch_finalize(F, c->stream));
+    HIPCHK(c, launch_reduce_finalize(F, c->partials, c->grid, c->ncols, c->red, c->stream));
     HIPCHK(c, hipMemcpyAsync(ll, c->scal, 8, hipMemcpyDeviceToHost, c->stream));
     if ((st = sync(c)) != EM_OK) return st;
     c->sigma2E = sigma2;
@@ -773,7 +770,6 @@ em_status em_loglik_bwd(em_ctx *c, double g, double *grad_a_dev, double *grad_si
                             c->logrho32E, c->logrho64E, 2.0 / c->sigma2E, nullptr, nullptr,
                             nullptr, true, false);
     if (st != EM_OK) return st;
-    HIPCHK(c, launch_reduce(c->partials, c->grid, c->ncols, c->red, c->stream));
     FinArgs F = fin_base(c, FIN_GRAD);
     F.sigma2 = c->sigma2E;
     F.a_in = c->aE;
@@ -781,7 +777,7 @@ em_status em_loglik_bwd(em_ctx *c, double g, double *grad_a_dev, double *grad_si
     F.g = g;
     F.grad_a = grad_a_dev;
     F.grad_eta = grad_eta_dev;
-    HIPCHK(c, launch_finalize(F, c->stream));
+    HIPCHK(c, launch_reduce_finalize(F, c->partials, c->grid, c->ncols, c->red, c->stream));
     double gs = 0;
     HIPCHK(c, hipMemcpyAsync(&gs, c->scal + 1, 8, hipMemcpyDeviceToHost, c->stream));
     if ((st = sync(c)) != EM_OK) return st;

@@ -108,7 +108,10 @@ hipError_t launch_scale(const double *in, double *out, int n, double factor, hip
 hipError_t launch_template(const TplArgs &a, hipStream_t s);
 hipError_t launch_pass(int prec, int BM, int WM, int LD, const PassArgs &a, int grid, size_t lds,
                        hipStream_t s);
-hipError_t launch_finalize(const FinArgs &a, hipStream_t s);
+// The fixed-order sum of G rows of ncols partials into red, then the finalize on red (F.red must
+// be red).
+hipError_t launch_reduce_finalize(const FinArgs &a, const double *partials, int G, int ncols,
+                                  double *red, hipStream_t s);
 hipError_t launch_softmax(const double *eta, double *rho, float *logrho32, double *logrho64,
                           int W, int Wp, hipStream_t s);
 hipError_t launch_logrho(const double *rho, float *logrho32, double *logrho64, int W, int Wp,

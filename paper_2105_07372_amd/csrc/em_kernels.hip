@@ -6,11 +6,12 @@
 //                    l_ji = 2 C_ji / sigma^2 + log rho_i, per-row log-sum-exp, posteriors,
 //                    U_jk = sum_i w_ji exp(+i k theta_i), S_d += sum_j U_{j,kbar_d} v_jd,
 //                    W_i += sum_j w_ji; FP64 per-workgroup partials
-//   reduce_kernel    fixed-order FP64 sum of the partials
+//   reduce_kernel    fixed-order FP64 sum of the partials (set-up sums)
+//   reduce_cols_kernel  the same sum of a pass's partials, more workgroups per column
 //   finalize_kernel  FP64: a_{t+1}, rho_{t+1}, log-likelihood, MAP objective, stopping metric
 //
 // The per-row constants -(||v_j||^2 + ||a||^2)/sigma^2 - D log(pi sigma^2) of the log-weights are
-// left out of the pass (they cancel in the posteriors) and added back in FP64 in finalize_kernel.
+// left out of the pass (they cancel in the posteriors) and added back in FP64 in the finalize.
 #include "em_internal.h"
 
 #include <math.h>
@@ -2102,34 +2103,46 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
 }
 
 // ------------------------------------------------------------------------------------------
-// a6: FP64 finalize (one workgroup of kFinThreads).
+// a6: FP64 reduction of the workgroup partials (reduce_cols_kernel: kRedCols columns per
+// workgroup, all G rows in a fixed order), then the FP64 finalize in one workgroup.
 
 constexpr int kFinThreads = 512;
+constexpr int kFinWaves = kFinThreads / 64;
+constexpr int kRedCols = 16;                       // partial columns per reducing workgroup
 constexpr int kFinPhaseLds = 2048;                 // phase table staged in LDS up to this L
 
-// Deterministic block sums of NV doubles per thread in one pass (fixed tree order).
-template <int NV>
-__device__ __forceinline__ void block_sum_multi(double (&v)[NV], double *sh) {
-    const int t = threadIdx.x;
+// Deterministic workgroup sums (OP = 0) or maxima (OP = 1) of NV doubles per thread: a butterfly
+// over the wave's 64 lanes (every lane ends with the same value), then the kFinWaves wave results
+// in wave order.  sh holds NV x kFinWaves doubles; every thread must call it.
+template <int NV, int OP = 0>
+__device__ __forceinline__ void fin_block_reduce(double (&v)[NV], double *sh) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            const double o = __shfl_xor(v[k], m);
+            v[k] = OP ? fmax(v[k], o) : v[k] + o;
+        }
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) sh[k * kFinWaves + wave] = v[k];
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < NV; ++k) sh[k * kFinThreads + t] = v[k];
-    __syncthreads();
-    for (int s = kFinThreads >> 1; s > 0; s >>= 1) {
-        if (t < s)
-#pragma unroll
-            for (int k = 0; k < NV; ++k) sh[k * kFinThreads + t] += sh[k * kFinThreads + t + s];
-        __syncthreads();
+    for (int k = 0; k < NV; ++k) {
+        double t = sh[k * kFinWaves];
+        for (int w = 1; w < kFinWaves; ++w)
+            t = OP ? fmax(t, sh[k * kFinWaves + w]) : t + sh[k * kFinWaves + w];
+        v[k] = t;
     }
-#pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] = sh[k * kFinThreads];
-    __syncthreads();
 }
 
-__global__ __launch_bounds__(kFinThreads) void finalize_kernel(FinArgs F) {
-    if (F.mode == FIN_EM && *F.stopped) return;
-    __shared__ double sh[5 * kFinThreads];
+// The finalize proper (one workgroup), on the reduced sums in F.red.
+__device__ void finalize_body(const FinArgs &F) {
+    __shared__ double sh[8 * kFinWaves];
     __shared__ double2 anew[kMaxD];
+    __shared__ double2 ain[kMaxD];
     __shared__ double2 ck[kMaxK];
     __shared__ double2 ph[kFinPhaseLds];
     const int t = threadIdx.x;
@@ -2143,7 +2156,7 @@ __global__ __launch_bounds__(kFinThreads) void finalize_kernel(FinArgs F) {
     if (F.mode != FIN_EM) {
         double v[1] = {0.0};
         for (int r = t; r < 2 * D; r += kFinThreads) v[0] += F.a_in[r] * F.a_in[r];
-        block_sum_multi<1>(v, sh);
+        fin_block_reduce<1>(v, sh);
         const double an2 = v[0];
         const double ll = s_lse - (F.sum_vn2 + N * an2) / F.sigma2 -
                           N * (double)D * log(M_PI * F.sigma2);
@@ -2164,92 +2177,148 @@ __global__ __launch_bounds__(kFinThreads) void finalize_kernel(FinArgs F) {
         return;
     }
 
-    // FIN_EM.  Pass 1: ||a_t||^2, MAP prior terms, a_{t+1}, ||a_{t+1}||^2, ||a_{t+1} - a_t||^2,
-    // the rho normaliser; phase table into LDS.
+    // FIN_EM.  Every input (a_t, S, the prior terms, W_t, the phase table, t, the stop flag) is
+    // loaded up front, so the workgroup waits on global memory once.
+    constexpr int DPF = kMaxD / kFinThreads, WPF = kMaxWp / kFinThreads;
     const bool ph_lds = L <= kFinPhaseLds;
-    if (ph_lds)
+    if (ph_lds) {
+#pragma unroll 4
         for (int m = t; m < L; m += kFinThreads) ph[m] = F.phase[m];
+    }
+    double2 at[DPF], sd[DPF];
+    double gv[DPF];
+#pragma unroll
+    for (int c = 0; c < DPF; ++c) {
+        const int d = t + c * kFinThreads;
+        at[c] = sd[c] = make_double2(0.0, 0.0);
+        gv[c] = 0.0;
+        if (d < D) {
+            at[c] = ((const double2 *)F.a_in)[d];
+            sd[c] = ((const double2 *)S)[d];
+            if (F.gai) gv[c] = F.gai[d];
+        }
+    }
+    double wt[WPF], rb[WPF], ri[WPF];
+#pragma unroll
+    for (int c = 0; c < WPF; ++c) {
+        const int i = t + c * kFinThreads;
+        wt[c] = rb[c] = 0.0;
+        ri[c] = 1.0;
+        if (i < W) {
+            wt[c] = Wt[i];
+            rb[c] = F.rho_bar[i];
+            ri[c] = F.rho_in[i];
+        }
+    }
+    const int64_t it = *F.t;
+    if (*F.stopped) return;
+
+    // ||a_t||^2, MAP prior terms, a_{t+1}, ||a_{t+1}||^2, ||a_{t+1} - a_t||^2, the rho normaliser
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int d = t; d < D; d += kFinThreads) {
-        const double ar = F.a_in[2 * d], ai = F.a_in[2 * d + 1];
-        const double g = F.gai ? F.gai[d] : 0.0;
-        const double den = N + F.sigma2 * g;
-        const double2 an = make_double2(S[2 * d] / den, S[2 * d + 1] / den);
-        anew[d] = an;
-        v[0] += ar * ar + ai * ai;
-        v[1] -= g * (ar * ar + ai * ai);
-        v[2] += an.x * an.x + an.y * an.y;
-        v[3] += (an.x - ar) * (an.x - ar) + (an.y - ai) * (an.y - ai);
+    double2 an[DPF];
+#pragma unroll
+    for (int c = 0; c < DPF; ++c) {
+        const int d = t + c * kFinThreads;
+        const double den = N + F.sigma2 * gv[c];
+        an[c] = make_double2(sd[c].x / den, sd[c].y / den);
+        if (d < D) {
+            const double ar = at[c].x, ai = at[c].y;
+            anew[d] = an[c];
+            ain[d] = at[c];
+            v[0] += ar * ar + ai * ai;
+            v[1] -= gv[c] * (ar * ar + ai * ai);
+            v[2] += an[c].x * an[c].x + an[c].y * an[c].y;
+            v[3] += (an[c].x - ar) * (an[c].x - ar) + (an[c].y - ai) * (an[c].y - ai);
+        }
     }
-    for (int i = t; i < W; i += kFinThreads) {
-        if (F.gamma != 0.0 && F.rho_bar[i] > 0.0) v[1] += F.gamma * F.rho_bar[i] * log(F.rho_in[i]);
-        v[4] += Wt[i] + F.gamma * F.rho_bar[i];
+#pragma unroll
+    for (int c = 0; c < WPF; ++c) {
+        if (t + c * kFinThreads >= W) continue;
+        if (F.gamma != 0.0 && rb[c] > 0.0) v[1] += F.gamma * rb[c] * log(ri[c]);
+        v[4] += wt[c] + F.gamma * rb[c];
     }
-    block_sum_multi<5>(v, sh);
+    fin_block_reduce<5>(v, sh);                 // its barriers also publish anew, ain, ph
     const double an2 = v[0], jprior = v[1], nn2 = v[2], dl2 = v[3], tot = v[4];
     const double ll = s_lse - (F.sum_vn2 + N * an2) / F.sigma2 -
                       N * (double)D * log(M_PI * F.sigma2);
 
-    // c_k = sum_q conj(a_new[k,q]) a_t[k,q]
-    for (int k = t; k < K; k += kFinThreads) {
+    // c_k = sum_q conj(a_new[k,q]) a_t[k,q]: 16 lanes per k (q = lane % 16, + 16, ...), their
+    // partial sums combined by a butterfly inside the 16-lane group
+    for (int k0 = 0; k0 < K; k0 += kFinThreads / 16) {
+        const int k = k0 + t / 16, qp = t % 16;
         double cr = 0.0, ci = 0.0;
-        for (int q = 0; q < F.Q; ++q) {
-            const int d = k * F.Q + q;
-            const double2 an = anew[d];
-            const double ar = F.a_in[2 * d], ai = F.a_in[2 * d + 1];
-            cr += an.x * ar + an.y * ai;
-            ci += an.x * ai - an.y * ar;
+        if (k < K)
+            for (int q = qp; q < F.Q; q += 16) {
+                const int d = k * F.Q + q;
+                const double2 a1 = anew[d], a0 = ain[d];
+                cr += a1.x * a0.x + a1.y * a0.y;
+                ci += a1.x * a0.y - a1.y * a0.x;
+            }
+#pragma unroll
+        for (int m = 8; m >= 1; m >>= 1) {
+            cr += __shfl_xor(cr, m);
+            ci += __shfl_xor(ci, m);
         }
-        ck[k] = make_double2(cr, ci);
+        if (k < K && qp == 0) ck[k] = make_double2(cr, ci);
     }
     __syncthreads();
-    // Pass 2: stopping metric min_l ||a_new - exp(-2 pi i kbar l / L) a_t||^2 and the entropy
-    // of rho_{t+1}
+    // stopping metric min_l ||a_new - exp(-2 pi i kbar l / L) a_t||^2 and the entropy of rho_{t+1}
+    // (the phase table read from LDS or, for L above kFinPhaseLds, from global memory: two loops,
+    // so that neither reads through a generic pointer)
     double best = INFINITY;
     for (int l = t; l < L; l += kFinThreads) {
         double re = 0.0;
         int m = 0;                                          // (k l) mod L, incrementally
-        for (int k = 0; k < K; ++k) {
-            const double2 p = ph_lds ? ph[m] : F.phase[m];   // exp(+2 pi i k l / L)
-            re += ck[k].x * p.x + ck[k].y * p.y;             // Re(c_k exp(-2 pi i k l / L))
-            m += l;
-            if (m >= L) m -= L;
+        if (ph_lds) {
+#pragma unroll 8
+            for (int k = 0; k < K; ++k) {
+                const double2 p = ph[m];                     // exp(+2 pi i k l / L)
+                re += ck[k].x * p.x + ck[k].y * p.y;         // Re(c_k exp(-2 pi i k l / L))
+                m += l;
+                if (m >= L) m -= L;
+            }
+        } else {
+#pragma unroll 8
+            for (int k = 0; k < K; ++k) {
+                const double2 p = F.phase[m];
+                re += ck[k].x * p.x + ck[k].y * p.y;
+                m += l;
+                if (m >= L) m -= L;
+            }
         }
         best = fmin(best, nn2 + an2 - 2.0 * re);
     }
-    double ent = 0.0;
-    for (int i = t; i < W; i += kFinThreads) {
-        const double rn = F.update_rho ? (Wt[i] + F.gamma * F.rho_bar[i]) / tot : F.rho_in[i];
-        if (rn > 0.0) ent -= rn * log(rn);
+    double rn[WPF], ent = 0.0;
+#pragma unroll
+    for (int c = 0; c < WPF; ++c) {
+        rn[c] = F.update_rho ? (wt[c] + F.gamma * rb[c]) / tot : ri[c];
+        if (t + c * kFinThreads < W && rn[c] > 0.0) ent -= rn[c] * log(rn[c]);
     }
     {
-        double w2[2] = {-best, ent};
-        // min via max of negatives, with the same fixed tree as the sums
-        __syncthreads();
-        sh[t] = w2[0];
-        sh[kFinThreads + t] = w2[1];
-        __syncthreads();
-        for (int s = kFinThreads >> 1; s > 0; s >>= 1) {
-            if (t < s) {
-                sh[t] = fmax(sh[t], sh[t + s]);
-                sh[kFinThreads + t] += sh[kFinThreads + t + s];
-            }
-            __syncthreads();
-        }
-        best = -sh[0];
-        ent = sh[kFinThreads];
-        __syncthreads();
+        double mx[1] = {-best};
+        fin_block_reduce<1, 1>(mx, sh);
+        best = -mx[0];
+        double e1[1] = {ent};
+        fin_block_reduce<1>(e1, sh + kFinWaves);
+        ent = e1[0];
     }
-    if (F.update_rho)
-        for (int i = t; i < W; i += kFinThreads) F.rho[i] = (Wt[i] + F.gamma * F.rho_bar[i]) / tot;
-    for (int d = t; d < D; d += kFinThreads) {
-        F.a[2 * d] = anew[d].x;
-        F.a[2 * d + 1] = anew[d].y;
+    // rho_{t+1} and its log (-inf on zero entries and on the padding up to Wp), a_{t+1}
+#pragma unroll
+    for (int c = 0; c < WPF; ++c) {
+        const int i = t + c * kFinThreads;
+        if (i >= F.Wp) continue;
+        const double r = i < W ? rn[c] : 0.0;
+        if (i < W && F.update_rho) F.rho[i] = r;
+        const double l = r > 0.0 ? log(r) : -INFINITY;
+        F.logrho32[i] = (float)l;
+        F.logrho64[i] = l;
     }
-    __syncthreads();
-    write_logrho(F.rho, F.logrho32, F.logrho64, W, F.Wp);
+#pragma unroll
+    for (int c = 0; c < DPF; ++c) {
+        const int d = t + c * kFinThreads;
+        if (d < D) ((double2 *)F.a)[d] = an[c];
+    }
     if (t == 0) {
-        const int64_t it = *F.t;
         double *rec = F.stats + (it % kStatsCap) * 6;
         rec[0] = (double)it;
         rec[1] = ll;
@@ -2262,6 +2331,36 @@ __global__ __launch_bounds__(kFinThreads) void finalize_kernel(FinArgs F) {
         if (F.tol > 0.0 && best < F.tol) *F.stopped = 1;
     }
 }
+
+// Fixed-order FP64 sum of a pass's partials: workgroup b sums columns [16 b, 16 b + 16) over the G
+// rows.  Thread t = 16 g + c takes column c of rows g, g + 32, ...; the four row groups of a wave
+// are combined by a butterfly (lanes 16 apart, then 32), then the eight waves in order.
+__global__ __launch_bounds__(kFinThreads) void reduce_cols_kernel(FinArgs F, const double *partials,
+                                                                  int G, int ncols, double *red) {
+    __shared__ double rsh[kFinWaves * kRedCols];
+    constexpr int NG = kFinThreads / kRedCols;
+    static_assert(kRedCols == 16 && NG == 32, "row groups: 4 per wave");
+    const int t = threadIdx.x, cl = t % kRedCols, gs = t / kRedCols, wave = t >> 6;
+    const int col = blockIdx.x * kRedCols + cl;
+    double s = 0.0;
+    if (col < ncols) {
+#pragma unroll 8
+        for (int b = gs; b < G; b += NG) s += partials[(int64_t)b * ncols + col];
+    }
+    s += __shfl_xor(s, 16);
+    s += __shfl_xor(s, 32);
+    if (F.mode == FIN_EM && *F.stopped) return;
+    if ((t & 63) < kRedCols) rsh[wave * kRedCols + cl] = s;
+    __syncthreads();
+    if (t < kRedCols && col < ncols) {
+        double u = rsh[t];
+#pragma unroll
+        for (int w = 1; w < kFinWaves; ++w) u += rsh[w * kRedCols + t];
+        red[col] = u;
+    }
+}
+
+__global__ __launch_bounds__(kFinThreads) void finalize_kernel(FinArgs F) { finalize_body(F); }
 
 // ------------------------------------------------------------------------------------------
 // a8: histogram of integer rotation errors (mod L).
@@ -2354,11 +2453,13 @@ hipError_t launch_template(const TplArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const FinArgs &a, hipStream_t s) {
+hipError_t launch_reduce_finalize(const FinArgs &a, const double *partials, int G, int ncols,
+                                  double *red, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_cols_kernel, dim3((ncols + kRedCols - 1) / kRedCols),
+                       dim3(kFinThreads), 0, s, a, partials, G, ncols, red);
     hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kFinThreads), 0, s, a);
     return hipGetLastError();
 }
-
 hipError_t launch_histogram(const int32_t *err, int64_t n, int L, unsigned long long *counts,
                             hipStream_t s) {
     int64_t blocks = (n + 255) / 256;

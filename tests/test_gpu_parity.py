@@ -42,6 +42,11 @@ def _case(name, seed=0):
     elif name == "wide":
         w = wl.WORKLOADS["c3"].replace(N=4099, K=32, Q=16, L=360, half_window=24)
         gamma = 100.0
+    elif name == "kodd":
+        # D = 507 (Q = 13 odd, D not a multiple of 4) and W = 41: the K-split pass with three
+        # column tiles and entries of one M-step lane spanning two frequencies
+        w = wl.WORKLOADS["c3"].replace(N=3001, K=39, Q=13, L=180, half_window=20)
+        gamma = 20.0
     else:
         raise KeyError(name)
     a_true = wl.image(w, seed)
@@ -73,7 +78,7 @@ def _compare_posteriors(em, V, a, rho, s2, w, lo, W, prec, row0=0, nrows=None):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp16", "bf16"])
-@pytest.mark.parametrize("case", ["window", "full", "odd", "wide"])
+@pytest.mark.parametrize("case", ["window", "full", "odd", "wide", "kodd"])
 def test_teacher_forced_step(gpu, prec, case):
     from paper_2105_07372_amd import EM
     w, a_true, V, s2, lo, W, rb, gamma = _case(case)
@@ -85,6 +90,8 @@ def test_teacher_forced_step(gpu, prec, case):
     print(f"case={case} prec={prec} N={w.N} D={w.D} L={w.L} W={W}", flush=True)
     em = EM(_obs(V, prec, gpu), K=w.K, Q=w.Q, L=w.L, sigma2=s2, window=(lo, W), prior=rb,
             gamma=gamma, precision=prec, gamma_a_inv=gai)
+    if case in ("wide", "kodd") and prec in ("bf16x3", "fp16", "bf16"):
+        assert em.info()["kernel"].startswith("pass_ks_kernel"), em.info()
     em.set_state(a_t, rho_t, 0)
     _compare_posteriors(em, V, a_t, rho_t, s2, w, lo, W, prec)
     ll_ref = oracle.loglik(V, a_t, rho_t, s2, w.kbar, w.L, oracle.offsets(lo, W))
