@@ -72,8 +72,8 @@ typedef struct {
     int64_t n_obs;          /* N >= 1                                                        */
     int32_t K, Q;           /* angular x radial sizes, D = K*Q in [1, 2048]                   */
     int32_t L;              /* rotation grid size >= 1                                        */
-    int32_t window_lo;      /* first offset (any integer; taken mod L)                        */
-    int32_t window_count;   /* W in [1, min(L, 1024)]                                         */
+    int32_t window_lo;      /* first offset (any integer; taken mod L); 0 when angles is set   */
+    int32_t window_count;   /* W in [1, min(L, 1024)]; with angles: W in [1, 1024]            */
     double  sigma2;         /* noise variance per complex entry, > 0                          */
     double  gamma;          /* weight of the KL prior on rho (Section III-B eq. (23)), >= 0   */
     int32_t update_rho;     /* 1: update rho each iteration (eq. (18) / the KL-prior update of
@@ -84,6 +84,13 @@ typedef struct {
                                    covariance of the Gaussian image prior of eq. (17); NULL: none */
     const double *a0;       /* host, 2D doubles: initial estimate; NULL: the mean of the
                                observations (Algorithm "Synch-EM", initialisation)               */
+    const double *angles;   /* host, W finite angles in radians: the rotations searched, in place
+                               of the grid offsets window_lo .. window_lo + W - 1 (the refined-
+                               resolution window of Section III-C: the likely range sampled more
+                               densely than the grid 2 pi / L).  The E-step, the M-step (eq. (17)
+                               with exp(+i k theta_i)) and rho (one entry per angle) use these
+                               angles; L still sets the grid of the stopping metric.  NULL: the
+                               grid window.                                                     */
 } em_params;
 
 /* Create a context and load the observations (Algorithm "Synch-EM", inputs and initialisation).

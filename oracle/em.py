@@ -5,6 +5,12 @@ angular index per entry ``kbar`` (D ints), rotation grid ``theta_l = 2 pi l / L`
 search (§III-C) visits the offsets ``o_i = lo + i`` (i = 0..W-1); plain EM is ``lo = 0, W = L``.
 ``rho`` has one entry per visited offset.  Rotating ``a`` by ``theta`` multiplies entry d by
 ``exp(-i kbar[d] theta)`` (§I eq. (3)).
+
+Wherever a function takes ``offs`` it also accepts an ``AngleList``: the refined-resolution
+window of §III-C, which samples the likely range of rotations more densely than the grid, so the
+visited rotations are arbitrary angles ``theta_i`` (radians) instead of ``2 pi o_i / L``.  The
+E-step, the M-step and rho are then the same formulas with ``exp(-/+ i kbar theta_i)``; ``L``
+still sets the grid of the stopping metric and of the error against the truth.
 """
 from __future__ import annotations
 
@@ -14,7 +20,7 @@ from typing import Optional
 import numpy as np
 
 __all__ = [
-    "offsets", "grid_phase", "rotate", "distances_brute", "distances", "log_weights", "normalize",
+    "AngleList", "offsets", "grid_phase", "rotate", "distances_brute", "distances", "log_weights", "normalize",
     "estep", "loglik", "mstep_a", "mstep_rho", "objective", "stop_metric", "em_iteration",
     "em_run", "relative_error", "grad_loglik", "histogram_prior", "argmax_margin",
     "q_function", "validate",
@@ -29,6 +35,16 @@ class OracleNonFinite(ValueError):
     """Raised for NaN/Inf observations (mirrors the library's EM_ENONFINITE)."""
 
 
+class AngleList:
+    """Visited rotations given as angles in radians (the refined-resolution window, §III-C)."""
+
+    def __init__(self, theta):
+        self.theta = np.asarray(theta, dtype=np.float64).ravel()
+
+    def __len__(self) -> int:
+        return len(self.theta)
+
+
 def offsets(lo: int, W: int) -> np.ndarray:
     """Window offsets lo..lo+W-1 (§III-C: angles -pi BW/L .. pi BW/L in steps of 2 pi/L)."""
     return np.arange(lo, lo + W, dtype=np.int64)
@@ -37,8 +53,11 @@ def offsets(lo: int, W: int) -> np.ndarray:
 def grid_phase(kbar: np.ndarray, l, L: int, sign: int) -> np.ndarray:
     """exp(sign * i * kbar * 2 pi l / L), evaluated at the exact grid angle 2 pi ((k l) mod L)/L.
 
-    ``l`` may be a scalar or a vector of offsets; the result has shape (..., D).
+    ``l`` may be a scalar or a vector of offsets, or an ``AngleList`` (then the phase is
+    exp(sign * i * kbar * theta_i) at the given angles); the result has shape (..., D).
     """
+    if isinstance(l, AngleList):
+        return np.exp(sign * 1j * np.multiply.outer(l.theta, np.asarray(kbar, dtype=np.float64)))
     l = np.asarray(l, dtype=np.int64)
     m = np.mod(np.multiply.outer(l, np.asarray(kbar, dtype=np.int64)), L)
     return np.exp(sign * 2j * np.pi * m / L)
@@ -49,6 +68,16 @@ def rotate(a: np.ndarray, kbar: np.ndarray, l: int, L: int) -> np.ndarray:
     return a * grid_phase(kbar, l, L, -1)
 
 
+def _rotated(a, kbar, offs, i: int, L: int) -> np.ndarray:
+    """R_{theta_i} a for the i-th visited rotation: the grid rotation for integer offsets; for an
+    ``AngleList``, entry by entry a_d (cos(k theta_i) - i sin(k theta_i)) with scalar math."""
+    if isinstance(offs, AngleList):
+        th = float(offs.theta[i])
+        return np.array([a[d] * complex(math.cos(int(kbar[d]) * th), -math.sin(int(kbar[d]) * th))
+                         for d in range(len(a))])
+    return rotate(a, kbar, int(offs[i]), L)
+
+
 def distances_brute(V, a, kbar, L, offs) -> np.ndarray:
     """r[j, i] = || R_{o_i} a - v_j ||^2 with the rotation applied explicitly (§II-B eq. (15)).
 
@@ -56,8 +85,8 @@ def distances_brute(V, a, kbar, L, offs) -> np.ndarray:
     """
     N, W = V.shape[0], len(offs)
     r = np.empty((N, W))
-    for i, o in enumerate(offs):
-        t = rotate(a, kbar, int(o), L)
+    for i in range(W):
+        t = _rotated(a, kbar, offs, i, L)
         for j in range(N):
             diff = t - V[j]
             r[j, i] = float(np.sum(diff.real ** 2 + diff.imag ** 2))
@@ -163,10 +192,10 @@ def q_function(a, rho, w, V, kbar, L, offs, sigma2, rho_bar=None, gamma=0.0,
     total = 0.0
     with np.errstate(divide="ignore"):
         for j in range(V.shape[0]):
-            for i, o in enumerate(offs):
+            for i in range(len(offs)):
                 if w[j, i] == 0.0:
                     continue
-                d = rotate(a, kbar, int(o), L) - V[j]
+                d = _rotated(a, kbar, offs, i, L) - V[j]
                 total += w[j, i] * (math.log(rho[i]) - float(np.sum(np.abs(d) ** 2)) / sigma2)
     if gamma_a_inv is not None:
         total -= float(np.sum(np.asarray(gamma_a_inv) * np.abs(a) ** 2))

@@ -30,7 +30,8 @@ class EmParams(C.Structure):
                 ("window_lo", C.c_int32), ("window_count", C.c_int32),
                 ("sigma2", C.c_double), ("gamma", C.c_double),
                 ("update_rho", C.c_int32), ("precision", C.c_int32), ("flags", C.c_uint64),
-                ("gamma_a_inv", C.POINTER(C.c_double)), ("a0", C.POINTER(C.c_double))]
+                ("gamma_a_inv", C.POINTER(C.c_double)), ("a0", C.POINTER(C.c_double)),
+                ("angles", C.POINTER(C.c_double))]
 
 
 class EmInfo(C.Structure):
@@ -113,7 +114,7 @@ class EM:
                  window: Optional[tuple[int, int]] = None, prior=None, gamma: float = 0.0,
                  update_rho: bool = True, precision: str = "fp32", gamma_a_inv=None, a0=None,
                  keep_lse: bool = False, timing: bool = False, general_pass: bool = False,
-                 wide_pass: bool = False, factored: bool = False,
+                 wide_pass: bool = False, factored: bool = False, angles=None,
                  stream=None):
         import torch
         lib = load()
@@ -123,6 +124,11 @@ class EM:
         if not (isinstance(obs, torch.Tensor) and obs.is_cuda and obs.dtype == want
                 and obs.dim() == 2 and obs.is_contiguous() and obs.shape[1] == K * Q):
             raise ValueError(f"obs must be a contiguous CUDA {want} tensor of shape (N, {K * Q})")
+        if angles is not None:
+            angles = np.ascontiguousarray(angles, dtype=np.float64).ravel()
+            if window is not None and tuple(window) != (0, len(angles)):
+                raise ValueError("with angles, window must be None or (0, len(angles))")
+            window = (0, len(angles))
         lo, W = (0, L) if window is None else window
         self.K, self.Q, self.D, self.L, self.lo, self.W = K, Q, K * Q, L, lo, W
         self.N = int(obs.shape[0])
@@ -145,6 +151,9 @@ class EM:
             a = np.ascontiguousarray(np.asarray(a0, dtype=np.complex128)).view(np.float64)
             keep.append(a)
             p.a0 = _dptr(a)
+        if angles is not None:
+            keep.append(angles)
+            p.angles = _dptr(angles)
         pr = None
         if prior is not None:
             pr = np.ascontiguousarray(prior, dtype=np.float64)

@@ -230,8 +230,14 @@ em_status check_params(const em_params *p) {
     if (p->n_obs < 1) return fail(nullptr, EM_EINVAL, "n_obs must be >= 1");
     if (p->K < 1 || p->Q < 1) return fail(nullptr, EM_EINVAL, "K and Q must be >= 1");
     if (p->L < 1) return fail(nullptr, EM_EINVAL, "L must be >= 1");
-    if (p->window_count < 1 || p->window_count > p->L)
+    if (p->angles) {
+        if (p->window_count < 1) return fail(nullptr, EM_EINVAL, "window_count must be >= 1");
+        if (p->window_lo != 0) return fail(nullptr, EM_EINVAL, "window_lo must be 0 with angles");
+        if (!finite_all(p->angles, p->window_count))
+            return fail(nullptr, EM_EINVAL, "angles must be finite");
+    } else if (p->window_count < 1 || p->window_count > p->L) {
         return fail(nullptr, EM_EINVAL, "window_count must be in [1, L]");
+    }
     if (!(p->sigma2 > 0) || !std::isfinite(p->sigma2))
         return fail(nullptr, EM_EINVAL, "sigma2 must be positive and finite");
     if (!(p->gamma >= 0) || !std::isfinite(p->gamma))
@@ -349,10 +355,8 @@ em_status run_template(em_ctx *c, const double *a, void *Thi, void *Tlo, float *
     T.Dp = c->Dp;
     T.W = c->W;
     T.Wp = c->Wp;
-    T.L = c->L;
-    T.lo = c->lo;
     T.prec = c->prec;
-    T.phase = c->phase;
+    T.E64 = c->E64;
     T.Thi = Thi;
     T.Tlo = Tlo;
     T.tscale = tscale;
@@ -552,10 +556,16 @@ em_status em_init(em_ctx **out, const em_params *p, const void *obs_dev, const d
     std::vector<double2> e64((size_t)c->Wp * c->K, make_double2(0.0, 0.0));
     for (int i = 0; i < c->W; ++i)
         for (int k = 0; k < c->K; ++k) {
-            const int64_t m = ((int64_t)k * (c->lo + i)) % c->L;
-            e64[(size_t)i * c->K + k] = ph[m];
-            e2[(size_t)i * 2 * c->K + k] = (float)ph[m].x;
-            e2[(size_t)i * 2 * c->K + c->K + k] = (float)ph[m].y;
+            double2 e;
+            if (p->angles) {                          // exp(+i k theta_i) at the given angle
+                const long double ang = (long double)k * (long double)p->angles[i];
+                e = make_double2((double)cosl(ang), (double)sinl(ang));
+            } else {                                  // the exact grid angle 2 pi ((k o_i) mod L) / L
+                e = ph[((int64_t)k * (c->lo + i)) % c->L];
+            }
+            e64[(size_t)i * c->K + k] = e;
+            e2[(size_t)i * 2 * c->K + k] = (float)e.x;
+            e2[(size_t)i * 2 * c->K + c->K + k] = (float)e.y;
         }
     std::vector<float> l32;
     std::vector<double> l64;

@@ -90,8 +90,8 @@ struct FinArgs {
 
 struct TplArgs {
     const double *a;
-    int D, K, Q, Dp, W, Wp, L, lo, prec;
-    const double2 *phase;
+    int D, K, Q, Dp, W, Wp, prec;
+    const double2 *E64;        // Wp x K: exp(+i k theta_i)
     void *Thi, *Tlo;
     float *tscale;
     const int *stopped;

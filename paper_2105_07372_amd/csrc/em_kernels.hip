@@ -276,9 +276,7 @@ __global__ __launch_bounds__(256) void template_kernel(TplArgs A) {
         double tre = 0.0, tim = 0.0;
         if (d < A.D && i < A.W) {
             const int k = d / A.Q;
-            int64_t m = ((int64_t)k * (A.lo + i)) % A.L;
-            if (m < 0) m += A.L;
-            const double2 ph = A.phase[m];             // exp(+2 pi i m / L)
+            const double2 ph = A.E64[(int64_t)i * A.K + k];   // exp(+i k theta_i)
             const double are = A.a[2 * d], aim = A.a[2 * d + 1];
             tre = (are * ph.x + aim * ph.y) * sc;      // a * conj(ph)
             tim = (aim * ph.x - are * ph.y) * sc;

@@ -81,6 +81,28 @@ def test_init_rejects_bad_prior_and_pointers(lib):
     assert lib.em_init(C.byref(ctx), C.byref(p), FAKE, None, None) == B.EM_EINVAL
 
 
+def test_init_validates_angle_lists(lib):
+    """The refined-resolution window: finite angles, window_lo 0; W is not bounded by L."""
+    ctx = C.c_void_p()
+    p = _params()                              # window_lo = -3
+    ang = np.linspace(-0.2, 0.2, 7)
+    p.angles = B._dptr(ang)
+    assert lib.em_init(C.byref(ctx), C.byref(p), FAKE, None, None) == B.EM_EINVAL
+    assert "window_lo" in lib.em_last_error(None).decode()
+    p.window_lo = 0
+    bad = ang.copy()
+    bad[3] = np.nan
+    p.angles = B._dptr(bad)
+    assert lib.em_init(C.byref(ctx), C.byref(p), FAKE, None, None) == B.EM_EINVAL
+    assert "angles" in lib.em_last_error(None).decode()
+    many = np.linspace(-0.5, 0.5, 48)           # W = 48 > L = 36 is allowed with angles
+    p.window_count = 48
+    p.angles = B._dptr(many)
+    p.sigma2 = 0.0                               # ... so the check after the window's fails
+    assert lib.em_init(C.byref(ctx), C.byref(p), FAKE, None, None) == B.EM_EINVAL
+    assert "sigma2" in lib.em_last_error(None).decode()
+
+
 def test_null_context_calls_are_rejected(lib):
     d = C.c_double(0.0)
     assert lib.em_step(None, 1, 0.0, None, None) == B.EM_EINVAL
@@ -101,6 +123,6 @@ def test_learn_prior_validates_before_device_work(lib):
 
 
 def test_struct_layout_matches_header():
-    assert C.sizeof(B.EmParams) == 80
+    assert C.sizeof(B.EmParams) == 88
     assert B.EmParams.sigma2.offset == 32 and B.EmParams.flags.offset == 56
-    assert B.EmParams.a0.offset == 72
+    assert B.EmParams.a0.offset == 72 and B.EmParams.angles.offset == 80

@@ -41,6 +41,68 @@ def test_vectorised_distances_match_explicit_rotation(window):
     assert np.max(np.abs(rb - rv)) <= 1e-12 * np.max(np.abs(rb))
 
 
+# ---------------------------------------------------------------- refined-resolution window (§III-C)
+
+def _refined(L, W, step):
+    """W angles centred on 0, `step` grid steps (2 pi / L) apart: a window sampled more densely
+    than the grid when step < 1 (§III-C)."""
+    return oracle.AngleList((np.arange(W) - W // 2) * step * 2 * np.pi / L)
+
+
+def test_angle_list_on_the_grid_is_the_offset_window():
+    """Angles 2 pi o_i / L listed explicitly give the offset window's posteriors, log-likelihood
+    and M-step (the table-free angle path against the exact grid phases)."""
+    p = _problem(window=(-3, 7))
+    ang = oracle.AngleList(2 * np.pi * p["offs"] / p["L"])
+    args = (p["V"], p["a0"], p["rho"], p["s2"], p["kbar"], p["L"])
+    w1, l1, _ = oracle.estep(*args, p["offs"])
+    w2, l2, _ = oracle.estep(*args, ang)
+    assert np.max(np.abs(w1 - w2)) <= 1e-13
+    assert np.max(np.abs(l1 - l2)) <= 1e-12 * np.max(np.abs(l1))
+    a1, _ = oracle.mstep_a(p["V"], w1, p["kbar"], p["L"], p["offs"], p["s2"])
+    a2, _ = oracle.mstep_a(p["V"], w2, p["kbar"], p["L"], ang, p["s2"])
+    assert np.max(np.abs(a1 - a2)) <= 1e-13 * np.max(np.abs(a1))
+
+
+@pytest.mark.parametrize("step", [0.5, 0.37])
+def test_angle_list_distances_match_explicit_rotation(step):
+    """Off-grid angles: the matmul distances equal those of the rotation applied entry by entry
+    with scalar cos/sin (eq. (15))."""
+    p = _problem(L=12)
+    ang = _refined(12, 9, step)
+    rb = oracle.distances_brute(p["V"], p["a0"], p["kbar"], 12, ang)
+    rv = oracle.distances(p["V"], p["a0"], p["kbar"], 12, ang)
+    assert np.max(np.abs(rb - rv)) <= 1e-12 * np.max(np.abs(rb))
+
+
+def test_refined_window_noiseless_exact_recovery():
+    """Observations rotated by listed off-grid angles, no noise, s2 -> 0 at the true image: each
+    posterior row is one-hot on its observation's own angle, and one M-step (eq. (17) with
+    exp(+i k theta_i)) returns the image exactly."""
+    K, Q, L, N, W = 4, 3, 12, 20, 9
+    p = _problem(K=K, Q=Q, N=N, L=L)
+    a, kbar = p["a"], p["kbar"]
+    ang = _refined(L, W, 0.37)
+    c = np.random.default_rng(4).integers(0, W, N)
+    V = np.stack([a * np.exp(-1j * kbar * ang.theta[ci]) for ci in c])
+    rho = np.full(W, 1.0 / W)
+    w, _, _ = oracle.estep(V, a, rho, 1e-8, kbar, L, ang)
+    assert np.array_equal(np.argmax(w, axis=1), c)
+    assert np.max(np.abs(w.max(axis=1) - 1.0)) <= 1e-12
+    a1, _ = oracle.mstep_a(V, w, kbar, L, ang, 1e-8)
+    assert np.max(np.abs(a1 - a)) <= 1e-12 * np.max(np.abs(a))
+
+
+def test_loglik_never_decreases_refined_window():
+    """EM over a refined window (half-step angles) never decreases the log-likelihood."""
+    p = _problem(K=6, Q=4, N=300, L=24, snr=0.3, seed=5)
+    ang = _refined(24, 15, 0.5)
+    rho = np.full(15, 1 / 15)
+    _, _, hist = oracle.em_run(p["V"], p["a0"], rho, p["s2"], p["kbar"], 24, ang, 30)
+    ll = [h["ll"] for h in hist]
+    assert all(b >= a - 1e-10 * abs(a) for a, b in zip(ll, ll[1:]))
+
+
 def test_pixel_rotation_matches_coefficient_phase():
     """Rotating the sampled image by shifting its angle axis equals multiplying a_kq by
     exp(-i k theta) (§I eq. (3)); the pixel-domain distances equal the coefficient ones."""
@@ -100,11 +162,14 @@ def _perturb_dirs(D, rng, n=6):
     return [(rng.standard_normal(D) + 1j * rng.standard_normal(D)) for _ in range(n)]
 
 
-@pytest.mark.parametrize("with_prior", [False, True])
-def test_coefficient_update_maximises_q(with_prior):
+@pytest.mark.parametrize("with_prior,refined", [(False, False), (True, False), (False, True)])
+def test_coefficient_update_maximises_q(with_prior, refined):
     """The closed form of eq. (17) is the maximiser of Q (eq. (14)) over a: Q written out term
-    by term is lower at every perturbation and its finite-difference gradient vanishes."""
+    by term is lower at every perturbation and its finite-difference gradient vanishes.  Also for
+    a refined window of off-grid angles (Q then rotates by explicit cos/sin of k theta_i)."""
     p = _problem(K=3, Q=2, N=6, L=8, window=(-2, 5))
+    if refined:
+        p["offs"] = _refined(8, 5, 0.41)
     D = p["D"]
     gai = np.linspace(0.3, 2.0, D) if with_prior else None
     w, _, _ = oracle.estep(p["V"], p["a0"], p["rho"], p["s2"], p["kbar"], p["L"], p["offs"])
