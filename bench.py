@@ -163,10 +163,20 @@ def main():
     runs = [(f"windowed_{p}", dict(precision=p)) for p in ("fp16",) if args.precision != "fp16"]
     # the factored E-step (per-frequency sums, an exact rewrite of the correlation)
     runs += [(f"windowed_factored_{p}", dict(precision=p, factored=True)) for p in ("fp32", "fp16")]
+    # the refined-resolution window (Section III-C): as many angles as the window, sampled at
+    # half-degree steps over the central +-12 degrees, prior shaped like the rotation law there
+    ang = (np.arange(W) - W // 2) * np.pi / w.L
+    rb_ang = np.exp(-0.5 * (np.degrees(ang) / w.rot_std_deg) ** 2)
+    rb_ang /= rb_ang.sum()
+    runs += [(f"windowed_refined_{args.precision}",
+              dict(precision=args.precision, angles=ang, prior=rb_ang))]
     for name, kw in runs:
-        e2 = EM(obs, K=w.K, Q=w.Q, L=w.L, sigma2=s2, window=(lo, W), prior=rb, gamma=w.gamma,
-                timing=True, **kw)
-        d2, p2, _ = time_em(e2, args.steps, args.warmup, (a0, rb, 0))
+        kw = dict(kw)
+        pr = kw.pop("prior", rb)
+        if "angles" not in kw:
+            kw["window"] = (lo, W)
+        e2 = EM(obs, K=w.K, Q=w.Q, L=w.L, sigma2=s2, prior=pr, gamma=w.gamma, timing=True, **kw)
+        d2, p2, _ = time_em(e2, args.steps, args.warmup, (a0, pr, 0))
         variants[name] = {"iter_per_s": args.steps / d2, "pass_us": p2 * 1e3,
                           "kernel": e2.info()["kernel"],
                           "hbm_frac": float(w.N) * e2.info()["bytes_per_row"] / (p2 * 1e-3) / 1e9
