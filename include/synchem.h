@@ -162,6 +162,48 @@ em_status em_get_stats(em_ctx *ctx, double *buf, int32_t cap, int32_t *n);
 em_status em_learn_prior(const int32_t *err_dev, int64_t n, int32_t L, int32_t lo, int32_t W,
                          double *rho_bar, int64_t *counts, int64_t *n_in_window, void *stream);
 
+/* ---- Synchronize and Match: the step before the EM path (§II-A, §III-A).
+ * These calls take the caller's observations directly (device, N x D complex64, row-major, the
+ * same layout as em_init; not copied), run on stream and synchronise it, allocate their own
+ * scratch and free it before returning.  Failures are reported through em_last_error(NULL).
+ * Observations must be finite (not checked here; em_init checks them).  Ties in an argmax or
+ * argmin go to the lowest index.  Sign conventions: R_l v = v o exp(-i kbar 2 pi l / L); rel[i][j]
+ * is the grid rotation that best maps v_j onto v_i, an estimate of theta_i - theta_j; the
+ * alignment multiplies by exp(+i kbar theta_i). */
+
+/* Relative rotations between all pairs of the first P observations (§II-A, the pairwise
+ * estimate): rel[i*P + j] = argmax_l Re <v_i, R_l v_j> over l = 0..L-1, computed through the
+ * per-frequency sums c_ijk = sum_q conj(v_ikq) v_jkq and FP32 matrix cores.  Optional outputs
+ * (device, P x P, may be NULL): gap = the best correlation minus the runner-up, dot = Re <v_i, v_j>
+ * (the l = 0 correlation).  2 <= P <= 8192, 1 <= L <= 4096, D <= 2048, K <= 512. */
+em_status em_relative_rotations(const void *obs_dev, int64_t P, int32_t K, int32_t Q, int32_t L,
+                                int32_t *rel_dev, float *gap_dev, float *dot_dev, void *stream);
+
+/* Projected power method of angular synchronization (§II-A): from z = 1, iters times
+ * z <- phase(H z) with H_ij = exp(+i 2 pi rel_ij / L) (FP64; an entry with H z = 0 keeps its
+ * value); theta_dev (device, P doubles) = arg z in [-pi, pi]. */
+em_status em_ppm(const int32_t *rel_dev, int64_t P, int32_t L, int32_t iters, double *theta_dev,
+                 void *stream);
+
+/* Nearest neighbours (Algorithm "Synchronize and Match", the matching step): for every
+ * observation i < N the member n of S_P = {0 .. P-1}, n != i, minimising ||v_i - v_n||^2 (no
+ * rotation; FP32 matrix cores).  nn_dev: N int32; gap_dev (N floats or NULL): the runner-up's
+ * squared distance minus the best.  2 <= P <= N; D a multiple of 8. */
+em_status em_nearest(const void *obs_dev, int64_t N, int32_t K, int32_t Q, int64_t P,
+                     int32_t *nn_dev, float *gap_dev, void *stream);
+
+/* Algorithm "Synchronize and Match": relative rotations and the power method (iters iterations)
+ * on S_P = the first P observations, then theta_i = phi_{nn_i} for every observation.
+ * theta_dev: N doubles (radians); nn_dev: N int32 or NULL. */
+em_status em_sync_match(const void *obs_dev, int64_t N, int32_t K, int32_t Q, int32_t L,
+                        int64_t P, int32_t iters, double *theta_dev, int32_t *nn_dev,
+                        void *stream);
+
+/* Aligned observations (§II-A): out[i] = v_i o exp(+i kbar theta_i), complex64, N x D (may not
+ * alias obs_dev). */
+em_status em_align(const void *obs_dev, int64_t N, int32_t K, int32_t Q, const double *theta_dev,
+                   void *out_dev, void *stream);
+
 /* Change the stream of later calls. */
 em_status em_set_stream(em_ctx *ctx, void *stream);
 

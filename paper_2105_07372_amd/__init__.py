@@ -5,8 +5,12 @@ The EM iteration (plain full search and the windowed, prior-weighted form) runs 
 
 * ``binding.EM``            one EM problem resident on the GPU (em_init / em_step / queries)
 * ``binding.learn_prior``   histogram prior over the window from integer rotation errors
+* ``binding.sync_match``    Synchronize and Match (relative rotations, power method, nearest
+                            neighbours), ``binding.align`` the aligned observations
 * ``autograd.marginal_loglik``  differentiable marginal log-likelihood with a hand-written adjoint
 """
-from .binding import EM, SynchemError, learn_prior, load  # noqa: F401
+from .binding import (EM, SynchemError, align, learn_prior, load, nearest, ppm,  # noqa: F401
+                      relative_rotations, sync_match)
 
-__all__ = ["EM", "SynchemError", "learn_prior", "load"]
+__all__ = ["EM", "SynchemError", "align", "learn_prior", "load", "nearest", "ppm",
+           "relative_rotations", "sync_match"]

@@ -69,6 +69,11 @@ def load() -> C.CDLL:
         "em_loglik_bwd": (i32, [vp, dbl, vp, P(dbl), vp]),
         "em_get_stats": (i32, [vp, P(dbl), i32, P(i32)]),
         "em_learn_prior": (i32, [vp, i64, i32, i32, i32, P(dbl), P(i64), P(i64), vp]),
+        "em_relative_rotations": (i32, [vp, i64, i32, i32, i32, vp, vp, vp, vp]),
+        "em_ppm": (i32, [vp, i64, i32, i32, vp, vp]),
+        "em_nearest": (i32, [vp, i64, i32, i32, i64, vp, vp, vp]),
+        "em_sync_match": (i32, [vp, i64, i32, i32, i32, i64, i32, vp, vp, vp]),
+        "em_align": (i32, [vp, i64, i32, i32, vp, vp, vp]),
         "em_set_stream": (i32, [vp, vp]),
         "em_pass_time": (i32, [vp, P(dbl), P(i64), i32]),
         "em_get_info": (i32, [vp, P(EmInfo)]),
@@ -289,3 +294,85 @@ def learn_prior(errors, L: int, lo: int, W: int, stream=None):
                                C.c_void_p(_stream_handle(stream)))
     _check(st, None)
     return rb, cnt, nin.value
+
+
+# ---- Synchronize and Match (the step before the EM path)
+
+def _obs_c64(obs, K: int, Q: int):
+    import torch
+    if not (isinstance(obs, torch.Tensor) and obs.is_cuda and obs.dtype == torch.complex64
+            and obs.dim() == 2 and obs.is_contiguous() and obs.shape[1] == K * Q):
+        raise ValueError(f"obs must be a contiguous CUDA complex64 tensor of shape (N, {K * Q})")
+    return C.c_void_p(obs.data_ptr())
+
+
+def relative_rotations(obs, K: int, Q: int, L: int, P: Optional[int] = None, stream=None):
+    """Relative rotations of all pairs of the first P rows of obs: (rel [P, P] int32, gap [P, P],
+    dot [P, P]) as CUDA tensors (em_relative_rotations)."""
+    import torch
+    P = int(obs.shape[0]) if P is None else int(P)
+    rel = torch.empty((P, P), dtype=torch.int32, device=obs.device)
+    gap = torch.empty((P, P), dtype=torch.float32, device=obs.device)
+    dot = torch.empty((P, P), dtype=torch.float32, device=obs.device)
+    st = load().em_relative_rotations(_obs_c64(obs, K, Q), P, int(K), int(Q), int(L),
+                                      C.c_void_p(rel.data_ptr()), C.c_void_p(gap.data_ptr()),
+                                      C.c_void_p(dot.data_ptr()),
+                                      C.c_void_p(_stream_handle(stream)))
+    _check(st, None)
+    return rel, gap, dot
+
+
+def ppm(rel, L: int, iters: int, stream=None):
+    """Projected power method on a [P, P] int32 CUDA tensor of relative rotations: theta [P]
+    (float64 CUDA tensor, radians) (em_ppm)."""
+    import torch
+    if not (rel.is_cuda and rel.dtype == torch.int32 and rel.is_contiguous() and rel.dim() == 2
+            and rel.shape[0] == rel.shape[1]):
+        raise ValueError("rel must be a square contiguous CUDA int32 tensor")
+    P = int(rel.shape[0])
+    th = torch.empty(P, dtype=torch.float64, device=rel.device)
+    st = load().em_ppm(C.c_void_p(rel.data_ptr()), P, int(L), int(iters),
+                       C.c_void_p(th.data_ptr()), C.c_void_p(_stream_handle(stream)))
+    _check(st, None)
+    return th
+
+
+def nearest(obs, K: int, Q: int, P: int, stream=None):
+    """Nearest member of the first P rows for every row (itself excluded): (nn [N] int32, gap [N]
+    float32) (em_nearest)."""
+    import torch
+    N = int(obs.shape[0])
+    nn = torch.empty(N, dtype=torch.int32, device=obs.device)
+    gap = torch.empty(N, dtype=torch.float32, device=obs.device)
+    st = load().em_nearest(_obs_c64(obs, K, Q), N, int(K), int(Q), int(P),
+                           C.c_void_p(nn.data_ptr()), C.c_void_p(gap.data_ptr()),
+                           C.c_void_p(_stream_handle(stream)))
+    _check(st, None)
+    return nn, gap
+
+
+def sync_match(obs, K: int, Q: int, L: int, P: int, iters: int = 50, stream=None):
+    """Synchronize and Match: (theta [N] float64, nn [N] int32) CUDA tensors (em_sync_match)."""
+    import torch
+    N = int(obs.shape[0])
+    th = torch.empty(N, dtype=torch.float64, device=obs.device)
+    nn = torch.empty(N, dtype=torch.int32, device=obs.device)
+    st = load().em_sync_match(_obs_c64(obs, K, Q), N, int(K), int(Q), int(L), int(P), int(iters),
+                              C.c_void_p(th.data_ptr()), C.c_void_p(nn.data_ptr()),
+                              C.c_void_p(_stream_handle(stream)))
+    _check(st, None)
+    return th, nn
+
+
+def align(obs, K: int, Q: int, theta, stream=None):
+    """Aligned observations v_i o exp(+i kbar theta_i) as a new complex64 CUDA tensor (em_align)."""
+    import torch
+    if not (theta.is_cuda and theta.dtype == torch.float64 and theta.is_contiguous()
+            and theta.numel() == obs.shape[0]):
+        raise ValueError("theta must be a contiguous CUDA float64 tensor with one entry per row")
+    out = torch.empty_like(obs)
+    st = load().em_align(_obs_c64(obs, K, Q), int(obs.shape[0]), int(K), int(Q),
+                         C.c_void_p(theta.data_ptr()), C.c_void_p(out.data_ptr()),
+                         C.c_void_p(_stream_handle(stream)))
+    _check(st, None)
+    return out

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libsynchem.so")
 BUILD = os.path.join(PKG, "_build")
-SOURCES = ["em_kernels.hip", "em_api.cpp"]
+SOURCES = ["em_kernels.hip", "sync_kernels.hip", "em_api.cpp"]
 ARCH = os.environ.get("SYNCHEM_ARCH", "gfx950")
 
 

@@ -846,6 +846,157 @@ em_status em_learn_prior(const int32_t *err_dev, int64_t n, int32_t L, int32_t l
     return EM_OK;
 }
 
+// ------------------------------------------------------------------------------------------
+// Synchronize and Match (§II-A, §III-A)
+
+namespace {
+
+struct DevBufs {                      // device scratch of one call, freed on every return path
+    std::vector<void *> p;
+    ~DevBufs() {
+        for (void *q : p) (void)hipFree(q);
+    }
+    bool get(void **out, size_t bytes) {
+        void *q = nullptr;
+        if (hipMalloc(&q, bytes + 16) != hipSuccess) return false;
+        p.push_back(q);
+        *out = q;
+        return true;
+    }
+};
+
+em_status sync_shape(int64_t N, int32_t K, int32_t Q) {
+    if (N < 1) return fail(nullptr, EM_EINVAL, "the number of observations must be >= 1");
+    if (K < 1 || Q < 1) return fail(nullptr, EM_EINVAL, "K and Q must be >= 1");
+    if ((int64_t)K * Q > kMaxD) return fail(nullptr, EM_EUNSUPPORTED, "D = K*Q above 2048");
+    if (K > kMaxK) return fail(nullptr, EM_EUNSUPPORTED, "K above 512");
+    return EM_OK;
+}
+
+em_status hip_status(hipError_t e, const char *what) {
+    if (e == hipSuccess) return EM_OK;
+    return fail(nullptr, EM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace
+
+em_status em_relative_rotations(const void *obs_dev, int64_t P, int32_t K, int32_t Q, int32_t L,
+                                int32_t *rel_dev, float *gap_dev, float *dot_dev, void *stream) {
+    g_err.clear();
+    em_status st = sync_shape(P, K, Q);
+    if (st != EM_OK) return st;
+    if (!obs_dev || !rel_dev) return fail(nullptr, EM_EINVAL, "obs_dev and rel_dev are required");
+    if (P < 2) return fail(nullptr, EM_EINVAL, "P must be >= 2");
+    if (P > kMaxSyncP) return fail(nullptr, EM_EUNSUPPORTED, "P above 8192");
+    if (L < 1 || L > kMaxSyncL) return fail(nullptr, EM_EINVAL, "L must be in [1, 4096]");
+    hipStream_t s = (hipStream_t)stream;
+    const int Lp = (L + 15) / 16 * 16, K2 = (2 * K + 3) / 4 * 4;
+    std::vector<float> B((size_t)Lp * K2, 0.f);
+    for (int l = 0; l < L; ++l)
+        for (int k = 0; k < K; ++k) {
+            const long double ang =
+                2.0L * 3.14159265358979323846264338327950288L * (((int64_t)k * l) % L) / L;
+            B[(size_t)l * K2 + k] = (float)cosl(ang);
+            B[(size_t)l * K2 + K + k] = (float)sinl(ang);
+        }
+    DevBufs buf;
+    float *Bd = nullptr, *gap = gap_dev, *dot = dot_dev;
+    if (!buf.get((void **)&Bd, B.size() * sizeof(float)) || (!gap && !buf.get((void **)&gap, (size_t)P * P * sizeof(float))) ||
+        (!dot && !buf.get((void **)&dot, (size_t)P * P * sizeof(float))))
+        return fail(nullptr, EM_ENOMEM, "hipMalloc failed");
+    hipError_t e = hipMemcpyAsync(Bd, B.data(), B.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = launch_relrot((const float2 *)obs_dev, (int)P, K, Q, L, Bd, rel_dev, gap, dot, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return hip_status(e, "relative rotations");
+}
+
+em_status em_ppm(const int32_t *rel_dev, int64_t P, int32_t L, int32_t iters, double *theta_dev,
+                 void *stream) {
+    g_err.clear();
+    if (!rel_dev || !theta_dev) return fail(nullptr, EM_EINVAL, "rel_dev and theta_dev are required");
+    if (P < 1) return fail(nullptr, EM_EINVAL, "P must be >= 1");
+    if (P > kMaxSyncP) return fail(nullptr, EM_EUNSUPPORTED, "P above 8192");
+    if (L < 1 || L > kMaxSyncL) return fail(nullptr, EM_EINVAL, "L must be in [1, 4096]");
+    if (iters < 0 || iters > 100000) return fail(nullptr, EM_EINVAL, "iters must be in [0, 100000]");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<double2> ph(L);
+    for (int m = 0; m < L; ++m) {
+        const long double ang = 2.0L * 3.14159265358979323846264338327950288L * m / L;
+        ph[m] = make_double2((double)cosl(ang), (double)sinl(ang));
+    }
+    DevBufs buf;
+    double2 *phd = nullptr, *z0 = nullptr, *z1 = nullptr;
+    if (!buf.get((void **)&phd, (size_t)L * sizeof(double2)) || !buf.get((void **)&z0, (size_t)P * sizeof(double2)) || !buf.get((void **)&z1, (size_t)P * sizeof(double2)))
+        return fail(nullptr, EM_ENOMEM, "hipMalloc failed");
+    hipError_t e = hipMemcpyAsync(phd, ph.data(), ph.size() * sizeof(double2),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_ppm(rel_dev, (int)P, L, phd, z0, z1, iters, theta_dev, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return hip_status(e, "power method");
+}
+
+em_status em_nearest(const void *obs_dev, int64_t N, int32_t K, int32_t Q, int64_t P,
+                     int32_t *nn_dev, float *gap_dev, void *stream) {
+    g_err.clear();
+    em_status st = sync_shape(N, K, Q);
+    if (st != EM_OK) return st;
+    if (!obs_dev || !nn_dev) return fail(nullptr, EM_EINVAL, "obs_dev and nn_dev are required");
+    if (P < 2 || P > N) return fail(nullptr, EM_EINVAL, "P must be in [2, N]");
+    if (P > (1 << 30)) return fail(nullptr, EM_EUNSUPPORTED, "P above 2^30");
+    if (((int64_t)K * Q) % 8 != 0)
+        return fail(nullptr, EM_EUNSUPPORTED, "nearest neighbours need D = K*Q a multiple of 8");
+    hipStream_t s = (hipStream_t)stream;
+    DevBufs buf;
+    float *nrm = nullptr, *gap = gap_dev;
+    if (!buf.get((void **)&nrm, (size_t)P * sizeof(float)) || (!gap && !buf.get((void **)&gap, (size_t)N * sizeof(float))))
+        return fail(nullptr, EM_ENOMEM, "hipMalloc failed");
+    hipError_t e = launch_nearest((const float2 *)obs_dev, N, P, K * Q, nrm, nn_dev, gap, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return hip_status(e, "nearest neighbours");
+}
+
+em_status em_sync_match(const void *obs_dev, int64_t N, int32_t K, int32_t Q, int32_t L,
+                        int64_t P, int32_t iters, double *theta_dev, int32_t *nn_dev,
+                        void *stream) {
+    g_err.clear();
+    em_status st = sync_shape(N, K, Q);
+    if (st != EM_OK) return st;
+    if (!obs_dev || !theta_dev) return fail(nullptr, EM_EINVAL, "obs_dev and theta_dev are required");
+    if (P < 2 || P > N) return fail(nullptr, EM_EINVAL, "P must be in [2, N]");
+    if (P > kMaxSyncP) return fail(nullptr, EM_EUNSUPPORTED, "P above 8192");
+    if (L < 1 || L > kMaxSyncL) return fail(nullptr, EM_EINVAL, "L must be in [1, 4096]");
+    if (iters < 0 || iters > 100000) return fail(nullptr, EM_EINVAL, "iters must be in [0, 100000]");
+    if (((int64_t)K * Q) % 8 != 0)
+        return fail(nullptr, EM_EUNSUPPORTED, "nearest neighbours need D = K*Q a multiple of 8");
+    hipStream_t s = (hipStream_t)stream;
+    DevBufs buf;
+    int32_t *rel = nullptr, *nn = nn_dev;
+    double *phi = nullptr;
+    if (!buf.get((void **)&rel, (size_t)P * P * sizeof(int32_t)) || !buf.get((void **)&phi, (size_t)P * sizeof(double)) || (!nn && !buf.get((void **)&nn, (size_t)N * sizeof(int32_t))))
+        return fail(nullptr, EM_ENOMEM, "hipMalloc failed");
+    if ((st = em_relative_rotations(obs_dev, P, K, Q, L, rel, nullptr, nullptr, stream)) != EM_OK)
+        return st;
+    if ((st = em_ppm(rel, P, L, iters, phi, stream)) != EM_OK) return st;
+    if ((st = em_nearest(obs_dev, N, K, Q, P, nn, nullptr, stream)) != EM_OK) return st;
+    hipError_t e = launch_gather(phi, P, nn, N, theta_dev, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return hip_status(e, "gather");
+}
+
+em_status em_align(const void *obs_dev, int64_t N, int32_t K, int32_t Q, const double *theta_dev,
+                   void *out_dev, void *stream) {
+    g_err.clear();
+    em_status st = sync_shape(N, K, Q);
+    if (st != EM_OK) return st;
+    if (!obs_dev || !theta_dev || !out_dev)
+        return fail(nullptr, EM_EINVAL, "obs_dev, theta_dev and out_dev are required");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_align((const float2 *)obs_dev, N, K, Q, theta_dev, (float2 *)out_dev, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return hip_status(e, "align");
+}
+
 em_status em_set_stream(em_ctx *c, void *stream) {
     if (!c) return fail(nullptr, EM_EINVAL, "ctx is NULL");
     c->stream = (hipStream_t)stream;

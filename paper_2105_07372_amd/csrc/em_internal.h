@@ -21,6 +21,8 @@ enum FinMode : int { FIN_EM = 0, FIN_LL = 1, FIN_GRAD = 2 };
 constexpr int kThreads = 512;        // threads per workgroup of the E+M pass (8 wave64)
 constexpr int kMaxDPerThread = 4;    // D <= 4 * kThreads
 constexpr int kMaxD = kMaxDPerThread * kThreads;
+constexpr int kMaxSyncP = 8192;      // Synchronize and Match: subset size
+constexpr int kMaxSyncL = 4096;      // ... and rotation grid
 constexpr int kMaxWp = 1024;         // padded window <= 2 * kThreads
 constexpr int kMaxK = 512;
 constexpr int kStatsCap = 1024;
@@ -112,6 +114,17 @@ hipError_t launch_pass(int prec, int BM, int WM, int LD, const PassArgs &a, int 
 // be red).
 hipError_t launch_reduce_finalize(const FinArgs &a, const double *partials, int G, int ncols,
                                   double *red, hipStream_t s);
+// Synchronize and Match (sync_kernels.hip).  B: Lp x K2 floats of cos | sin (see relrot_kernel).
+hipError_t launch_relrot(const float2 *V, int P, int K, int Q, int L, const float *B, int *rel,
+                         float *gap, float *dot0, hipStream_t s);
+hipError_t launch_ppm(const int *rel, int P, int L, const double2 *ph, double2 *z0, double2 *z1,
+                      int iters, double *theta, hipStream_t s);
+hipError_t launch_nearest(const float2 *V, int64_t N, int64_t P, int D, float *nrm, int *nn,
+                          float *gap, hipStream_t s);
+hipError_t launch_gather(const double *phi, int64_t P, const int *nn, int64_t N, double *theta,
+                         hipStream_t s);
+hipError_t launch_align(const float2 *V, int64_t N, int K, int Q, const double *theta,
+                        float2 *out, hipStream_t s);
 hipError_t launch_softmax(const double *eta, double *rho, float *logrho32, double *logrho64,
                           int W, int Wp, hipStream_t s);
 hipError_t launch_logrho(const double *rho, float *logrho32, double *logrho64, int W, int Wp,
