@@ -23,7 +23,8 @@ import numpy as np
 from .em import grid_phase
 
 __all__ = ["relative_rotations", "relative_rotations_brute", "ppm", "nearest_neighbours",
-           "synchronize_and_match", "align"]
+           "synchronize_and_match", "align", "aligned_mean", "global_rotation",
+           "centred_error_bins"]
 
 
 def relative_rotations(Vp: np.ndarray, kbar: np.ndarray, L: int):
@@ -100,3 +101,30 @@ def align(V: np.ndarray, kbar: np.ndarray, theta: np.ndarray) -> np.ndarray:
     """Aligned observations v_i o exp(+i kbar theta_i) (the steerable alignment of §II-A)."""
     return V * np.exp(1j * np.multiply.outer(np.asarray(theta, np.float64),
                                              np.asarray(kbar, np.float64)))
+
+
+# ---- learning the distribution of the synchronizer's errors (§III-B, Algorithm "learning
+# rotation distribution"; the histogram itself is em.histogram_prior)
+
+def aligned_mean(V: np.ndarray, kbar: np.ndarray, theta: np.ndarray) -> np.ndarray:
+    """(1/N) sum_i v_i o exp(+i kbar theta_i): the average of the aligned coefficients (§II-A),
+    which also starts the EM after synchronization (§III-A)."""
+    return align(V, kbar, theta).mean(axis=0)
+
+
+def global_rotation(x: np.ndarray, abar: np.ndarray, kbar: np.ndarray, L: int) -> int:
+    """The grid rotation theta_c = 2 pi l_c / L minimising || R_theta abar - x ||^2 (the
+    algorithm's centring step), i.e. argmax_l Re <x, R_l abar>; returns l_c."""
+    best, arg = -math.inf, 0
+    for l in range(L):
+        v = float(np.real(np.vdot(x, abar * grid_phase(kbar, l, L, -1))))
+        if v > best:
+            best, arg = v, l
+    return arg
+
+
+def centred_error_bins(theta_hat: np.ndarray, theta_true: np.ndarray, lc: int, L: int):
+    """floor((theta_hat - theta - theta_c) L / (2 pi)) mod L: the centred errors of the
+    algorithm, binned as in its histogram step (integer bins, then eq. (22) is the identity)."""
+    e = np.asarray(theta_hat, np.float64) - np.asarray(theta_true, np.float64) - 2 * np.pi * lc / L
+    return np.mod(np.floor(e * L / (2 * np.pi)).astype(np.int64), L)

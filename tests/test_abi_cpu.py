@@ -103,6 +103,29 @@ def test_init_validates_angle_lists(lib):
     assert "sigma2" in lib.em_last_error(None).decode()
 
 
+def test_sync_calls_validate_before_device_work(lib):
+    """Synchronize and Match entry points reject bad sizes and pointers without touching the
+    device (FAKE is never dereferenced)."""
+    st = B.STATUS_NAMES
+    ok = FAKE
+    assert lib.em_relative_rotations(None, 8, 4, 4, 36, ok, None, None, None) == B.EM_EINVAL
+    assert lib.em_relative_rotations(ok, 1, 4, 4, 36, ok, None, None, None) == B.EM_EINVAL
+    assert lib.em_relative_rotations(ok, 8, 4, 4, 0, ok, None, None, None) == B.EM_EINVAL
+    assert lib.em_relative_rotations(ok, 9000, 4, 4, 36, ok, None, None, None) == B.EM_EUNSUPPORTED
+    assert lib.em_relative_rotations(ok, 8, 64, 64, 36, ok, None, None, None) == B.EM_EUNSUPPORTED
+    assert lib.em_ppm(None, 8, 36, 5, ok, None) == B.EM_EINVAL
+    assert lib.em_ppm(ok, 8, 36, -1, ok, None) == B.EM_EINVAL
+    assert lib.em_nearest(ok, 100, 4, 4, 1, ok, None, None) == B.EM_EINVAL
+    assert lib.em_nearest(ok, 100, 4, 4, 101, ok, None, None) == B.EM_EINVAL
+    assert lib.em_nearest(ok, 100, 3, 3, 10, ok, None, None) == B.EM_EUNSUPPORTED
+    assert "multiple of 8" in lib.em_last_error(None).decode()
+    assert lib.em_sync_match(ok, 100, 4, 4, 36, 10, 5, None, None, None) == B.EM_EINVAL
+    assert lib.em_sync_match(ok, 100, 4, 4, 5000, 10, 5, ok, None, None) == B.EM_EINVAL
+    assert lib.em_align(ok, 0, 4, 4, ok, ok, None) == B.EM_EINVAL
+    assert lib.em_align(ok, 10, 4, 4, None, ok, None) == B.EM_EINVAL
+    assert st[B.EM_EINVAL]
+
+
 def test_null_context_calls_are_rejected(lib):
     d = C.c_double(0.0)
     assert lib.em_step(None, 1, 0.0, None, None) == B.EM_EINVAL

@@ -94,3 +94,23 @@ def test_align_undoes_a_grid_rotation(l):
     v = a * np.exp(-2j * np.pi * kbar * l / 12)
     assert np.max(np.abs(oracle.align(v[None], kbar, np.array([2 * np.pi * l / 12]))[0] - a)) \
         <= 1e-14 * np.abs(a).max()
+
+
+def test_global_rotation_and_centred_bins():
+    """The centring step finds an injected global rotation exactly; errors placed in the middle
+    of known bins come back as those bins (mod L)."""
+    V, a, kbar, _ = _data(N=1, noise=0.0, L=24)
+    for c in (0, 5, 17):
+        abar = a * np.exp(2j * np.pi * kbar * c / 24)          # R_{-c} a
+        assert oracle.global_rotation(a, abar, kbar, 24) == c
+    rng = np.random.default_rng(1)
+    th = rng.uniform(-np.pi, np.pi, 50)
+    m = rng.integers(-30, 30, 50)
+    th_hat = th + 2 * np.pi * (7 + m + 0.5) / 24
+    assert np.array_equal(oracle.centred_error_bins(th_hat, th, 7, 24), np.mod(m, 24))
+
+
+def test_aligned_mean_of_synchronized_noiseless_data_is_the_rotated_image():
+    V, a, kbar, l = _data(N=30, L=12, noise=0.0, seed=2)
+    th = 2 * np.pi * l / 12 + 0.3                              # exact up to a global 0.3 rad
+    assert np.max(np.abs(oracle.aligned_mean(V, kbar, th) - a * np.exp(0.3j * kbar))) <= 1e-13
