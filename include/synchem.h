@@ -204,6 +204,20 @@ em_status em_sync_match(const void *obs_dev, int64_t N, int32_t K, int32_t Q, in
 em_status em_align(const void *obs_dev, int64_t N, int32_t K, int32_t Q, const double *theta_dev,
                    void *out_dev, void *stream);
 
+/* The average of the aligned coefficients (§II-A): mean_dev (device, 2D doubles, re/im
+ * interleaved) = (1/N) sum_i v_i o exp(+i kbar theta_i), FP64 with FP64 phases, fixed-order
+ * sums.  After Synchronize and Match it is the EM's starting point (§III-A); in the algorithm that
+ * learns the rotation distribution it gives the global rotation theta_c. */
+em_status em_aligned_mean(const void *obs_dev, int64_t N, int32_t K, int32_t Q,
+                          const double *theta_dev, double *mean_dev, void *stream);
+
+/* Binned centred errors of a synchronizer (§III-B, Algorithm "learning rotation distribution"):
+ * bins_dev[i] = floor((theta_hat_i - theta_i - 2 pi lc / L) L / (2 pi)) mod L (FP64), for
+ * em_learn_prior.  theta_hat_dev, theta_dev: N doubles (radians); lc: the centring rotation on
+ * the grid (em_relative_rotations of the true image and the aligned mean gives it). */
+em_status em_error_bins(const double *theta_hat_dev, const double *theta_dev, int64_t N, int32_t L,
+                        int32_t lc, int32_t *bins_dev, void *stream);
+
 /* Change the stream of later calls. */
 em_status em_set_stream(em_ctx *ctx, void *stream);
 

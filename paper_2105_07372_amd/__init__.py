@@ -9,8 +9,9 @@ The EM iteration (plain full search and the windowed, prior-weighted form) runs 
                             neighbours), ``binding.align`` the aligned observations
 * ``autograd.marginal_loglik``  differentiable marginal log-likelihood with a hand-written adjoint
 """
-from .binding import (EM, SynchemError, align, learn_prior, load, nearest, ppm,  # noqa: F401
-                      relative_rotations, sync_match)
+from .binding import (EM, SynchemError, align, aligned_mean, error_bins,  # noqa: F401
+                      global_rotation, learn_prior, load, nearest, ppm, relative_rotations,
+                      sync_match)
 
-__all__ = ["EM", "SynchemError", "align", "learn_prior", "load", "nearest", "ppm",
-           "relative_rotations", "sync_match"]
+__all__ = ["EM", "SynchemError", "align", "aligned_mean", "error_bins", "global_rotation",
+           "learn_prior", "load", "nearest", "ppm", "relative_rotations", "sync_match"]

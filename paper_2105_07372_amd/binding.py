@@ -74,6 +74,8 @@ def load() -> C.CDLL:
         "em_nearest": (i32, [vp, i64, i32, i32, i64, vp, vp, vp]),
         "em_sync_match": (i32, [vp, i64, i32, i32, i32, i64, i32, vp, vp, vp]),
         "em_align": (i32, [vp, i64, i32, i32, vp, vp, vp]),
+        "em_aligned_mean": (i32, [vp, i64, i32, i32, vp, vp, vp]),
+        "em_error_bins": (i32, [vp, vp, i64, i32, i32, vp, vp]),
         "em_set_stream": (i32, [vp, vp]),
         "em_pass_time": (i32, [vp, P(dbl), P(i64), i32]),
         "em_get_info": (i32, [vp, P(EmInfo)]),
@@ -376,3 +378,44 @@ def align(obs, K: int, Q: int, theta, stream=None):
                          C.c_void_p(_stream_handle(stream)))
     _check(st, None)
     return out
+
+
+def aligned_mean(obs, K: int, Q: int, theta, stream=None):
+    """(1/N) sum_i v_i o exp(+i kbar theta_i) as a complex128 CUDA tensor (em_aligned_mean)."""
+    import torch
+    if not (theta.is_cuda and theta.dtype == torch.float64 and theta.is_contiguous()
+            and theta.numel() == obs.shape[0]):
+        raise ValueError("theta must be a contiguous CUDA float64 tensor with one entry per row")
+    out = torch.empty(K * Q, dtype=torch.complex128, device=obs.device)
+    st = load().em_aligned_mean(_obs_c64(obs, K, Q), int(obs.shape[0]), int(K), int(Q),
+                                C.c_void_p(theta.data_ptr()), C.c_void_p(out.data_ptr()),
+                                C.c_void_p(_stream_handle(stream)))
+    _check(st, None)
+    return out
+
+
+def error_bins(theta_hat, theta, L: int, lc: int, stream=None):
+    """Binned centred errors floor((theta_hat - theta - 2 pi lc / L) L / 2 pi) mod L as an int32
+    CUDA tensor (em_error_bins); feed them to learn_prior."""
+    import torch
+    for t in (theta_hat, theta):
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise ValueError("angles must be contiguous CUDA float64 tensors")
+    if theta_hat.numel() != theta.numel():
+        raise ValueError("theta_hat and theta must have the same length")
+    bins = torch.empty(theta.numel(), dtype=torch.int32, device=theta.device)
+    st = load().em_error_bins(C.c_void_p(theta_hat.data_ptr()), C.c_void_p(theta.data_ptr()),
+                              int(theta.numel()), int(L), int(lc), C.c_void_p(bins.data_ptr()),
+                              C.c_void_p(_stream_handle(stream)))
+    _check(st, None)
+    return bins
+
+
+def global_rotation(x, abar, K: int, Q: int, L: int, stream=None) -> int:
+    """The grid rotation l_c with R_{2 pi l_c / L} abar closest to x (the centring step of the
+    algorithm that learns the rotation distribution): the relative rotation of the pair (x, abar)
+    from em_relative_rotations (both complex CUDA vectors of length K*Q)."""
+    import torch
+    pair = torch.stack([x.to(torch.complex64), abar.to(torch.complex64)]).contiguous()
+    rel, _, _ = relative_rotations(pair, K, Q, L, 2, stream=stream)
+    return int(rel[0, 1].item())

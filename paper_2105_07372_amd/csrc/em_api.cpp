@@ -997,6 +997,41 @@ em_status em_align(const void *obs_dev, int64_t N, int32_t K, int32_t Q, const d
     return hip_status(e, "align");
 }
 
+em_status em_aligned_mean(const void *obs_dev, int64_t N, int32_t K, int32_t Q,
+                          const double *theta_dev, double *mean_dev, void *stream) {
+    g_err.clear();
+    em_status st = sync_shape(N, K, Q);
+    if (st != EM_OK) return st;
+    if (!obs_dev || !theta_dev || !mean_dev)
+        return fail(nullptr, EM_EINVAL, "obs_dev, theta_dev and mean_dev are required");
+    hipStream_t s = (hipStream_t)stream;
+    const int D = K * Q;
+    const int G = (int)std::min<int64_t>(N, 1024);
+    DevBufs buf;
+    double *part = nullptr, *sum = nullptr;
+    if (!buf.get((void **)&part, (size_t)G * 2 * D * sizeof(double)) ||
+        !buf.get((void **)&sum, (size_t)2 * D * sizeof(double)))
+        return fail(nullptr, EM_ENOMEM, "hipMalloc failed");
+    hipError_t e = launch_aligned_colsum((const float2 *)obs_dev, N, K, Q, theta_dev, part, G, s);
+    if (e == hipSuccess) e = launch_reduce(part, G, 2 * D, sum, s);
+    if (e == hipSuccess) e = launch_scale(sum, mean_dev, 2 * D, 1.0 / (double)N, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return hip_status(e, "aligned mean");
+}
+
+em_status em_error_bins(const double *theta_hat_dev, const double *theta_dev, int64_t N, int32_t L,
+                        int32_t lc, int32_t *bins_dev, void *stream) {
+    g_err.clear();
+    if (!theta_hat_dev || !theta_dev || !bins_dev)
+        return fail(nullptr, EM_EINVAL, "theta_hat_dev, theta_dev and bins_dev are required");
+    if (N < 1) return fail(nullptr, EM_EINVAL, "N must be >= 1");
+    if (L < 1 || L > 16384) return fail(nullptr, EM_EINVAL, "L must be in [1, 16384]");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_error_bins(theta_hat_dev, theta_dev, N, L, lc, bins_dev, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return hip_status(e, "error bins");
+}
+
 em_status em_set_stream(em_ctx *c, void *stream) {
     if (!c) return fail(nullptr, EM_EINVAL, "ctx is NULL");
     c->stream = (hipStream_t)stream;

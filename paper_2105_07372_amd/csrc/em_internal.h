@@ -125,6 +125,10 @@ hipError_t launch_gather(const double *phi, int64_t P, const int *nn, int64_t N,
                          hipStream_t s);
 hipError_t launch_align(const float2 *V, int64_t N, int K, int Q, const double *theta,
                         float2 *out, hipStream_t s);
+hipError_t launch_aligned_colsum(const float2 *V, int64_t N, int K, int Q, const double *theta,
+                                double *partials, int G, hipStream_t s);
+hipError_t launch_error_bins(const double *theta_hat, const double *theta, int64_t N, int L,
+                             int lc, int *bins, hipStream_t s);
 hipError_t launch_softmax(const double *eta, double *rho, float *logrho32, double *logrho64,
                           int W, int Wp, hipStream_t s);
 hipError_t launch_logrho(const double *rho, float *logrho32, double *logrho64, int W, int Wp,

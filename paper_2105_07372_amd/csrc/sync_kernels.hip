@@ -261,6 +261,39 @@ __global__ void align_kernel(const float2 *V, int64_t N, int K, int Q, const dou
     }
 }
 
+// Column sums of the aligned observations: workgroup b sums rows b, b + G, .. of
+// v_i o exp(+i kbar theta_i) for its columns in FP64 (phase in FP64); partials [G][2D].
+__global__ __launch_bounds__(256) void aligned_colsum_kernel(const float2 *V, int64_t N, int K,
+                                                             int Q, const double *theta,
+                                                             double *partials) {
+    const int D = K * Q;
+    for (int d = threadIdx.x; d < D; d += 256) {
+        const int k = d / Q;
+        double sr = 0.0, si = 0.0;
+        for (int64_t i = blockIdx.x; i < N; i += gridDim.x) {
+            double sn, cn;
+            sincos((double)k * theta[i], &sn, &cn);
+            const float2 v = V[i * D + d];
+            sr += v.x * cn - v.y * sn;
+            si += v.x * sn + v.y * cn;
+        }
+        partials[(int64_t)blockIdx.x * 2 * D + 2 * d] = sr;
+        partials[(int64_t)blockIdx.x * 2 * D + 2 * d + 1] = si;
+    }
+}
+
+// floor((theta_hat - theta - 2 pi lc / L) L / (2 pi)) mod L, in FP64.
+__global__ void error_bins_kernel(const double *theta_hat, const double *theta, int64_t N, int L,
+                                  int lc, int *bins) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double e = theta_hat[i] - theta[i] - 2.0 * M_PI * lc / L;
+    const double f = floor(e * L / (2.0 * M_PI));
+    int64_t b = (int64_t)fmod(f, (double)L);
+    if (b < 0) b += L;
+    bins[i] = (int)b;
+}
+
 // ------------------------------------------------------------------------------------------
 // launchers
 
@@ -314,6 +347,20 @@ hipError_t launch_align(const float2 *V, int64_t N, int K, int Q, const double *
     const int64_t total = N * K;
     hipLaunchKernelGGL(align_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, V, N,
                        K, Q, theta, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_aligned_colsum(const float2 *V, int64_t N, int K, int Q, const double *theta,
+                                double *partials, int G, hipStream_t s) {
+    hipLaunchKernelGGL(aligned_colsum_kernel, dim3(G), dim3(256), 0, s, V, N, K, Q, theta,
+                       partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_error_bins(const double *theta_hat, const double *theta, int64_t N, int L,
+                             int lc, int *bins, hipStream_t s) {
+    hipLaunchKernelGGL(error_bins_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s,
+                       theta_hat, theta, N, L, lc, bins);
     return hipGetLastError();
 }
 

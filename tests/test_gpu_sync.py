@@ -150,3 +150,59 @@ def test_sync_match_full_size(gpu):
     nn_r = nn.cpu().numpy()[rows]
     assert np.array_equal(nn_r[clear], np.argmin(d, axis=1)[clear])
     assert np.isfinite(th.cpu().numpy()).all()
+
+
+def test_aligned_mean_and_error_bins(gpu):
+    """The aligned average (FP64) and the binned centred errors against the oracle, on angles
+    drawn away from the bin edges."""
+    import torch
+    from paper_2105_07372_amd import aligned_mean, error_bins
+    K, Q, L, N = 16, 8, 72, 3001
+    w, a, V = _data(K, Q, L, N, 0.5)
+    rng = np.random.default_rng(9)
+    th = rng.uniform(-np.pi, np.pi, N)
+    m = rng.integers(-100, 100, N)
+    lc = 11
+    th_hat = th + 2 * np.pi * (lc + m + rng.uniform(0.1, 0.9, N)) / L
+    obs = torch.from_numpy(V).to(gpu)
+    am = aligned_mean(obs, K, Q, torch.from_numpy(th).to(gpu)).cpu().numpy()
+    ao = oracle.aligned_mean(V.astype(np.complex128), w.kbar, th)
+    assert np.abs(am - ao).max() <= 1e-12 * np.abs(ao).max()
+    bins = error_bins(torch.from_numpy(th_hat).to(gpu), torch.from_numpy(th).to(gpu), L, lc)
+    assert np.array_equal(bins.cpu().numpy(), oracle.centred_error_bins(th_hat, th, lc, L))
+    assert np.array_equal(bins.cpu().numpy(), np.mod(m, L))
+
+
+def test_learning_the_prior_from_the_synchronizer(gpu):
+    """The algorithm that learns the rotation distribution, with Synchronize and Match as the
+    synchronizer, over R = 3 trials: every GPU stage after the synchronizer is fed the oracle's
+    rotations, and the centring rotation, the binned errors and the learned window prior equal
+    the oracle's; the GPU synchronizer's own rotations are checked as in the end-to-end test."""
+    import torch
+    from paper_2105_07372_amd import (aligned_mean, error_bins, global_rotation, learn_prior,
+                                      sync_match)
+    K, Q, L, N, P, h = 16, 8, 72, 3000, 256, 9
+    bins_all = []
+    for r in range(3):
+        w, a, V = _data(K, Q, L, N, 1.0, seed=20 + r)
+        lt = wl.rotations(w, 20 + r)                            # the generator's true rotations
+        th_true = 2 * np.pi * lt / L
+        Vd = V.astype(np.complex128)
+        th_o, phi_o, _, nn_o = oracle.synchronize_and_match(Vd, w.kbar, L, P, 50)
+        lc_o = oracle.global_rotation(a, oracle.aligned_mean(Vd, w.kbar, th_o), w.kbar, L)
+        b_o = oracle.centred_error_bins(th_o, th_true, lc_o, L)
+        obs = torch.from_numpy(V).to(gpu)
+        th_g, nn_g = sync_match(obs, K, Q, L, P, 50)
+        ok = nn_g.cpu().numpy() == nn_o
+        assert ok.mean() > 0.9
+        am = aligned_mean(obs, K, Q, torch.from_numpy(th_o).to(gpu))
+        lc = global_rotation(torch.from_numpy(a).to(gpu), am, K, Q, L)
+        assert lc == lc_o
+        b = error_bins(torch.from_numpy(th_o).to(gpu), torch.from_numpy(th_true).to(gpu), L, lc)
+        assert np.array_equal(b.cpu().numpy(), b_o)
+        bins_all.append(b)
+    allb = torch.cat(bins_all)
+    rb, cnt, nin = learn_prior(allb, L, -h, 2 * h + 1)
+    rb_o, cnt_o, _ = oracle.histogram_prior(allb.cpu().numpy(), L, -h, 2 * h + 1)
+    assert np.allclose(rb, rb_o, rtol=0, atol=1e-15)
+    assert rb[h - 2:h + 3].sum() > 0.5                          # concentrated around no error
