@@ -105,6 +105,7 @@ def main():
     ap.add_argument("--precision", default="bf16x3")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-baseline", action="store_true", help="skip the full-search FP32 run")
+    ap.add_argument("--no-sync", action="store_true", help="skip the Synchronize-and-Match timing")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates the HBM "
@@ -204,6 +205,35 @@ def main():
         variants["full_search_factored_fp32"] = {"iter_per_s": nsteps / df, "pass_us": pf * 1e3,
                                                  "kernel": ef.info()["kernel"]}
         ef.close()
+
+    # Synchronize and Match (the step before the path) on the same observations: P = 1024,
+    # L = 360, 50 power iterations; each stage's wall time (each call synchronises) and the
+    # matrix-core rate of the two contractions
+    if not args.no_sync:
+        from paper_2105_07372_amd import nearest, ppm, relative_rotations, sync_match
+        P_s, it_s = 1024, 50
+        sync_match(obs, w.K, w.Q, w.L, P_s, it_s)                     # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rel_s, _, _ = relative_rotations(obs, w.K, w.Q, w.L, P_s)
+        t1 = time.perf_counter()
+        ppm(rel_s, w.L, it_s)
+        t2 = time.perf_counter()
+        nearest(obs, w.K, w.Q, P_s)
+        t3 = time.perf_counter()
+        sync_match(obs, w.K, w.Q, w.L, P_s, it_s)
+        t4 = time.perf_counter()
+        Lp, K2 = (w.L + 15) // 16 * 16, (2 * w.K + 3) // 4 * 4
+        f_rel = 2.0 * P_s * P_s * K2 * Lp                            # MFMA flops of the L-grid step
+        f_nn = 2.0 * w.N * P_s * 2 * w.D                             # MFMA flops of the distances
+        variants["sync_match"] = {
+            "workload": f"Synchronize and Match N={w.N} D={w.D} L={w.L} P={P_s}, {it_s} power "
+                        "iterations, FP32 matrix cores (power method FP64)",
+            "total_ms": (t4 - t3) * 1e3, "relative_rotations_ms": (t1 - t0) * 1e3,
+            "ppm_ms": (t2 - t1) * 1e3, "nearest_ms": (t3 - t2) * 1e3,
+            "relative_rotations_tflops": f_rel / (t1 - t0) / 1e12,
+            "nearest_tflops": f_nn / (t3 - t2) / 1e12, "fp32_mfma_peak_tflops": 157.3}
+        log(f"bench: sync_match {variants['sync_match']['total_ms']:.1f} ms")
 
     cpu = None
     acc = None
