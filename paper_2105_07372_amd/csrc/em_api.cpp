@@ -890,14 +890,19 @@ em_status em_relative_rotations(const void *obs_dev, int64_t P, int32_t K, int32
     if (P > kMaxSyncP) return fail(nullptr, EM_EUNSUPPORTED, "P above 8192");
     if (L < 1 || L > kMaxSyncL) return fail(nullptr, EM_EINVAL, "L must be in [1, 4096]");
     hipStream_t s = (hipStream_t)stream;
-    const int Lp = (L + 15) / 16 * 16, K2 = (2 * K + 3) / 4 * 4;
-    std::vector<float> B((size_t)Lp * K2, 0.f);
+    // B: Lp rows of [cos(k 2 pi l / L) | sin(k 2 pi l / L) | 0], row stride 64 for the tiled kernel
+    const int Lp = (L + 15) / 16 * 16, K2 = relrot_tiled(K, Q, L) ? 64 : (2 * K + 3) / 4 * 4;
+    std::vector<float> B((size_t)Lp * K2, 0.f), cs(L), sn(L);
+    for (int m = 0; m < L; ++m) {                 // the exact grid angles 2 pi m / L
+        const long double ang = 2.0L * 3.14159265358979323846264338327950288L * m / L;
+        cs[m] = (float)cosl(ang);
+        sn[m] = (float)sinl(ang);
+    }
     for (int l = 0; l < L; ++l)
         for (int k = 0; k < K; ++k) {
-            const long double ang =
-                2.0L * 3.14159265358979323846264338327950288L * (((int64_t)k * l) % L) / L;
-            B[(size_t)l * K2 + k] = (float)cosl(ang);
-            B[(size_t)l * K2 + K + k] = (float)sinl(ang);
+            const int m = (int)(((int64_t)k * l) % L);
+            B[(size_t)l * K2 + k] = cs[m];
+            B[(size_t)l * K2 + K + k] = sn[m];
         }
     DevBufs buf;
     float *Bd = nullptr, *gap = gap_dev, *dot = dot_dev;

@@ -115,6 +115,9 @@ hipError_t launch_pass(int prec, int BM, int WM, int LD, const PassArgs &a, int 
 hipError_t launch_reduce_finalize(const FinArgs &a, const double *partials, int G, int ncols,
                                   double *red, hipStream_t s);
 // Synchronize and Match (sync_kernels.hip).  B: Lp x K2 floats of cos | sin (see relrot_kernel).
+// true when the 16 x 16 pair-tile kernel serves (2K <= 64, Q % 8 == 0, L <= 384); its cos | sin
+// table then has row stride 64, else 2K rounded up to 4
+bool relrot_tiled(int K, int Q, int L);
 hipError_t launch_relrot(const float2 *V, int P, int K, int Q, int L, const float *B, int *rel,
                          float *gap, float *dot0, hipStream_t s);
 hipError_t launch_ppm(const int *rel, int P, int L, const double2 *ph, double2 *z0, double2 *z1,

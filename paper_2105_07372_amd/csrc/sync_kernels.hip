@@ -121,6 +121,117 @@ __global__ __launch_bounds__(kSyncThreads) void relrot_kernel(const float2 *V, i
     }
 }
 
+// The same estimate for a 16 x 16 tile of pairs (i in 16 it .., j in 16 jt ..) with both
+// contractions on FP32 matrix cores, for 2K <= 64 and Lp <= 384.
+//  1. c_ijk for the 256 pairs: per frequency k (wave w takes k = w, w + 4, ..) two real products
+//     over the 2Q interleaved reals of frequency k: Re c = [a_r a_i] . [b_r b_i] and
+//     Im c = [a_r a_i] . [b_i -b_r]; lane group g loads reals 16 s + 4 g .. + 3 of its i row (A)
+//     and j row (B) as one 16-byte read and feeds four MFMA k-steps (2Q a multiple of 16).
+//  2. f (256 pairs x Lp) = [Re c | Im c] . B^T: wave w owns the column tiles w, w + 4, .. (NW of
+//     them), their B fragments in registers for the whole workgroup; per 16-pair row tile m the
+//     A fragments come from LDS once and serve all the wave's column tiles; the top-2 of each
+//     pair is merged over the 16 lanes of a row group, then over the waves through LDS.
+template <int NW>
+__global__ __launch_bounds__(kSyncThreads) void relrot_tile_kernel(const float2 *V, int P, int K,
+                                                                   int Q, int L, int Lp,
+                                                                   const float *B, int *rel,
+                                                                   float *gap, float *dot0) {
+    constexpr int KK = 16, K2 = 64, CBW = K2 + 4;
+    __shared__ float cs[256 * CBW];
+    __shared__ Top2 red[4 * 256];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int g = lane >> 4, c = lane & 15;
+    const int i0 = blockIdx.y * 16, j0 = blockIdx.x * 16;
+    const int D = K * Q;
+    // ---- 1. per-frequency sums on matrix cores
+    for (int col = t; col < 256 * CBW; col += kSyncThreads) cs[col] = 0.f;
+    __syncthreads();
+    {
+        const int ia = i0 + c < P ? i0 + c : P - 1, jb = j0 + c < P ? j0 + c : P - 1;
+        const int NC = 2 * Q / 16;
+        for (int k = wave; k < K; k += 4) {
+            const float4 *pa = (const float4 *)(V + (int64_t)ia * D + k * Q);
+            const float4 *pb = (const float4 *)(V + (int64_t)jb * D + k * Q);
+            f32x4s cr = (f32x4s){0.f, 0.f, 0.f, 0.f}, ci = cr;
+            for (int sc = 0; sc < NC; ++sc) {
+                const float4 a = pa[4 * sc + g], b = pb[4 * sc + g];
+                // reals (x, y) and (z, w) are (re, im) pairs: [b_i, -b_r] per pair for Im
+                cr = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, cr, 0, 0, 0);
+                cr = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, cr, 0, 0, 0);
+                cr = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, cr, 0, 0, 0);
+                cr = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, cr, 0, 0, 0);
+                ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.y, ci, 0, 0, 0);
+                ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, -b.x, ci, 0, 0, 0);
+                ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.w, ci, 0, 0, 0);
+                ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, -b.z, ci, 0, 0, 0);
+            }
+            // cr[q] = Re c for i = i0 + 4 g + q, j = j0 + c
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int pr = (4 * g + q) * 16 + c;
+                cs[pr * CBW + k] = cr[q];
+                cs[pr * CBW + K + k] = ci[q];
+            }
+        }
+    }
+    __syncthreads();
+    // ---- 2. the L-grid correlations and their top-2
+    float bf[NW][KK];
+#pragma unroll
+    for (int u = 0; u < NW; ++u) {
+        const int n = wave + 4 * u;
+        const bool ok = 16 * n < Lp;
+        const float *bb = B + (int64_t)(ok ? 16 * n + c : 0) * K2;
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) bf[u][kk] = ok ? bb[4 * kk + g] : 0.f;
+    }
+    for (int m = 0; m < 16; ++m) {
+        float af[KK];
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) af[kk] = cs[(16 * m + c) * CBW + 4 * kk + g];
+        Top2 best[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) best[q] = Top2{-INFINITY, 0x7fffffff, -INFINITY};
+#pragma unroll
+        for (int u = 0; u < NW; ++u) {
+            const int n = wave + 4 * u;
+            if (16 * n >= Lp) break;
+            f32x4s acc = (f32x4s){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kk = 0; kk < KK; ++kk)
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[kk], bf[u][kk], acc, 0, 0, 0);
+            const int l = 16 * n + c;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (l < L) best[q] = top2_merge(best[q], Top2{acc[q], l, -INFINITY});
+                if (l == 0) {
+                    // pair (16 m + 4 g + q): i = i0 + (16 m + 4 g + q) / 16, j = j0 + .. % 16
+                    const int pr = 16 * m + 4 * g + q, ii = i0 + pr / 16, jj = j0 + pr % 16;
+                    if (ii < P && jj < P) dot0[(int64_t)ii * P + jj] = acc[q];
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int mm = 1; mm < 16; mm <<= 1)
+                best[q] = top2_merge(best[q], top2_shfl_xor(best[q], mm));
+        if (c == 0)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) red[wave * 256 + 16 * m + 4 * g + q] = best[q];
+    }
+    __syncthreads();
+    {
+        Top2 r = red[t];
+        for (int w = 1; w < 4; ++w) r = top2_merge(r, red[w * 256 + t]);
+        const int ii = i0 + t / 16, jj = j0 + t % 16;
+        if (ii < P && jj < P) {
+            rel[(int64_t)ii * P + jj] = r.i;
+            gap[(int64_t)ii * P + jj] = r.b - r.s;
+        }
+    }
+}
+
 // One projected power iteration: 4 rows per workgroup, 64 lanes per row summing j = lane,
 // lane + 64, .. in FP64, then a butterfly over the wave; z_out = y / |y| (z_in kept if y = 0).
 __global__ __launch_bounds__(kSyncThreads) void ppm_kernel(const int *rel, int P, int L,
@@ -302,9 +413,26 @@ size_t relrot_lds_bytes(int K, int Q) {
     return (size_t)((D * 8 + 15) / 16) * 16 + (size_t)16 * (K2 + 4) * 4 + 64 * sizeof(Top2);
 }
 
+bool relrot_tiled(int K, int Q, int L) {
+    const int Lp = (L + 15) / 16 * 16;
+    return (2 * K + 3) / 4 * 4 <= 64 && (2 * Q) % 16 == 0 && Lp <= 16 * 4 * 6;
+}
+
 hipError_t launch_relrot(const float2 *V, int P, int K, int Q, int L, const float *B, int *rel,
                          float *gap, float *dot0, hipStream_t s) {
     const int Lp = (L + 15) / 16 * 16, K2 = (2 * K + 3) / 4 * 4;
+    if (relrot_tiled(K, Q, L)) {
+        // B is laid out with row stride 64 for this kernel (see em_relative_rotations)
+        const int NT = Lp / 16, NW = (NT + 3) / 4;
+        const dim3 grid((P + 15) / 16, (P + 15) / 16);
+#define SEM_RT(W)                                                                                  case W:                                                                                            hipLaunchKernelGGL(relrot_tile_kernel<W>, grid, dim3(kSyncThreads), 0, s, V, P, K, Q, L,                            Lp, B, rel, gap, dot0);                                                     break;
+        switch (NW) {
+            SEM_RT(1) SEM_RT(2) SEM_RT(3) SEM_RT(4) SEM_RT(5) SEM_RT(6)
+        default: return hipErrorInvalidValue;
+        }
+#undef SEM_RT
+        return hipGetLastError();
+    }
     const size_t lds = relrot_lds_bytes(K, Q);
     hipError_t e = hipFuncSetAttribute((const void *)relrot_kernel,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
