@@ -22,7 +22,8 @@ import numpy as np
 __all__ = [
     "AngleList", "offsets", "grid_phase", "rotate", "distances_brute", "distances", "log_weights", "normalize",
     "estep", "loglik", "mstep_a", "mstep_rho", "objective", "stop_metric", "em_iteration",
-    "em_run", "relative_error", "grad_loglik", "histogram_prior", "argmax_margin",
+    "em_run", "relative_error", "relative_error_continuous",
+    "grad_loglik", "histogram_prior", "argmax_margin",
     "q_function", "validate",
 ]
 
@@ -252,6 +253,30 @@ def relative_error(a_hat, a_true, kbar, L) -> float:
     for l in range(L):
         best = min(best, float(np.linalg.norm(rotate(a_hat, kbar, l, L) - a_true)))
     return best / float(np.linalg.norm(a_true))
+
+
+def relative_error_continuous(a_hat, a_true, kbar, steps: int = 36000) -> float:
+    """min over all angles theta of ||a_hat o exp(-i kbar theta) - a_true|| / ||a_true|| (eq. (19)
+    over the continuous circle, for estimates whose global rotation is off the grid, as after
+    synchronization): the best of `steps` grid angles, then a golden-section refinement within
+    one grid step on either side."""
+    kb = np.asarray(kbar, np.float64)
+
+    def err(th):
+        return float(np.linalg.norm(a_hat * np.exp(-1j * kb * th) - a_true))
+
+    grid = 2 * np.pi * np.arange(steps) / steps
+    e = [err(t) for t in grid]
+    t0 = grid[int(np.argmin(e))]
+    lo, hi = t0 - 2 * np.pi / steps, t0 + 2 * np.pi / steps
+    r = (math.sqrt(5) - 1) / 2
+    for _ in range(60):
+        m1, m2 = hi - r * (hi - lo), lo + r * (hi - lo)
+        if err(m1) < err(m2):
+            hi = m2
+        else:
+            lo = m1
+    return min(err(0.5 * (lo + hi)), min(e)) / float(np.linalg.norm(a_true))
 
 
 def grad_loglik(V, a, sigma2, rho, kbar, L, offs):

@@ -126,6 +126,17 @@ int pow2_floor(int x) {
     return p;
 }
 
+// Waves over row blocks of the general pass for BM rows per tile: the eight waves split into
+// WM row groups x WN window groups (WN a power of two up to the window tiles).
+int pass_wm(int prec, int Wp, int BM) {
+    const int NT = Wp / 16;
+    const int WN = pow2_floor(NT < 8 ? NT : 8);
+    int WM = 8 / WN;
+    if (WM > BM / 16) WM = BM / 16 > 0 ? BM / 16 : 1;
+    if (prec == P_F64) WM = 1;
+    return WM;
+}
+
 // Choose rows per tile and the wave split of the pass for this problem.
 em_status plan(em_ctx *c, size_t lds_max) {
     c->ks = false;
@@ -191,8 +202,11 @@ em_status plan(em_ctx *c, size_t lds_max) {
             if (lds > lds_max) continue;
             if (BM > 16 && (int64_t)BM / 2 >= c->N) continue;          // tiny N: small tiles
             if (BM < 16 && LD) continue;
+            const int WM = pass_wm(c->prec, c->Wp, BM);
+            if (!pass_variant_exists(c->prec, BM, WM, LD)) continue;   // no kernel built for it
             c->BM = BM;
             c->LD = LD;
+            c->WM = WM;
             c->lds = lds;
             break;
         }
@@ -212,16 +226,8 @@ em_status plan(em_ctx *c, size_t lds_max) {
     }
     if (!c->BM)
         return fail(c, EM_EUNSUPPORTED,
-                    "observation rows too wide for this build (row of " +
-                        std::to_string(c->rowbytes) + " bytes does not fit the LDS tile)");
-    const int NT = c->Wp / 16;
-    const int WN = pow2_floor(NT < 8 ? NT : 8);
-    int WM = 8 / WN;
-    if (WM > c->BM / 16) WM = c->BM / 16 > 0 ? c->BM / 16 : 1;
-    if (c->prec == P_F64) WM = 1;
-    c->WM = WM;
-    if (!pass_variant_exists(c->prec, c->BM, c->WM, c->LD))
-        return fail(c, EM_EUNSUPPORTED, "no pass variant for this tile shape");
+                    "no E+M pass of this build fits rows of " + std::to_string(c->rowbytes) +
+                        " bytes with this window");
     return EM_OK;
 }
 

@@ -114,3 +114,11 @@ def test_aligned_mean_of_synchronized_noiseless_data_is_the_rotated_image():
     V, a, kbar, l = _data(N=30, L=12, noise=0.0, seed=2)
     th = 2 * np.pi * l / 12 + 0.3                              # exact up to a global 0.3 rad
     assert np.max(np.abs(oracle.aligned_mean(V, kbar, th) - a * np.exp(0.3j * kbar))) <= 1e-13
+
+
+def test_continuous_relative_error_removes_any_global_rotation():
+    V, a, kbar, _ = _data(N=1, noise=0.0, seed=4)
+    for th in (0.0, 0.123456, 2.5, -1.0):
+        assert oracle.relative_error_continuous(a * np.exp(-1j * kbar * th), a, kbar) <= 1e-9
+    b = a + 0.01 * np.exp(0.3j * kbar)
+    assert oracle.relative_error_continuous(b, a, kbar) <= np.linalg.norm(b - a) / np.linalg.norm(a)
