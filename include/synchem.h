@@ -70,7 +70,8 @@ typedef enum { EM_FP64 = 0, EM_FP32 = 1, EM_BF16X3 = 2, EM_FP16 = 3, EM_BF16 = 4
 
 typedef struct {
     int64_t n_obs;          /* N >= 1                                                        */
-    int32_t K, Q;           /* angular x radial sizes, D = K*Q in [1, 2048]                   */
+    int32_t K, Q;           /* angular x radial sizes, D = K*Q in [1, 2048]; EM_FP64, EM_FP32
+                               and EM_BF16X3 need D <= 512 (EM_EUNSUPPORTED above)         */
     int32_t L;              /* rotation grid size >= 1                                        */
     int32_t window_lo;      /* first offset (any integer; taken mod L); 0 when angles is set   */
     int32_t window_count;   /* W in [1, min(L, 1024)]; with angles: W in [1, 1024]            */
