@@ -92,3 +92,51 @@ def test_window_size_study(gpu):
         print(f"window h={h} (W={2 * h + 1}): err {errs[h]:.4f} in {it} iterations", flush=True)
     assert errs[12] <= errs[1]
     assert abs(errs[24] - errs[12]) <= 0.1 * errs[12] + 0.005
+
+
+def test_template_matching_is_the_posterior_argmax(gpu):
+    """Template matching against a reference (§II-A) is the argmax of the posterior with the
+    reference as the estimate and a uniform prior over all L rotations: it equals the oracle's
+    argmax_l Re <v_i, R_l ref> wherever the top two correlations are apart, and the observations
+    aligned by it average to the reference's rotation of the image."""
+    import torch
+    from paper_2105_07372_amd import EM
+    w, a, V, th, s2 = _problem(2)
+    ref = V[0].astype(np.complex128)
+    obs = torch.from_numpy(V).to(gpu)
+    em = EM(obs, K=K, Q=Q, L=L, sigma2=s2, precision="fp32", a0=ref)
+    _, am, mg = em.posterior()
+    em.close()
+    am = am.cpu().numpy()
+    C = np.real(np.conj(V.astype(np.complex128)) @ (ref[:, None] * oracle.grid_phase(
+        w.kbar, np.arange(L), L, -1).T))
+    s = np.sort(C, axis=1)
+    clear = s[:, -1] - s[:, -2] > 1e-4 * np.abs(C).max()
+    assert clear.mean() > 0.95
+    assert np.array_equal(am[clear], np.argmax(C, axis=1)[clear])
+
+
+def test_signal_prior_decay_study(gpu):
+    """The paper's study of the decay beta of the Gaussian image prior Gamma_a =
+    diag((4 exp(-kbar / beta))^2) (eq. (17)), with Synch-EM on synthetic data: each beta runs, and
+    a very strong prior (small beta) costs accuracy against a weak one."""
+    import torch
+    from paper_2105_07372_amd import EM, align, aligned_mean, sync_match
+    w, a, V, th, s2 = _problem(3)
+    obs = torch.from_numpy(V).to(gpu)
+    h = 12
+    rb, _ = _learned_prior(gpu, h, trials=2)
+    th_hat, _ = sync_match(obs, K, Q, L, P, 50)
+    al = align(obs, K, Q, th_hat)
+    a0 = aligned_mean(obs, K, Q, th_hat).cpu().numpy()
+    errs = {}
+    for beta in (0.5, 4.0, 8.0, 32.0):
+        gai = 1.0 / (4.0 * np.exp(-w.kbar / beta)) ** 2
+        em = EM(al, K=K, Q=Q, L=L, sigma2=s2, window=(-h, 2 * h + 1), prior=rb, gamma=100.0,
+                precision="fp32", a0=a0, gamma_a_inv=gai)
+        it, _ = em.step(400, tol=1e-5)
+        errs[beta] = oracle.relative_error_continuous(em.state()[0], a, w.kbar)
+        em.close()
+        print(f"beta={beta}: err {errs[beta]:.4f} in {it} iterations", flush=True)
+    assert all(np.isfinite(list(errs.values())))
+    assert errs[0.5] > errs[32.0]
