@@ -43,7 +43,7 @@ struct em_ctx {
     bool wide = false;    // wide-row pass (rows streamed through an LDS ring, 128-row tiles)
     int wNTW = 0, wUR = 0;
     bool fac = false;     // factored pass (per-frequency sums; no template)
-    int fWIDE = 0, fKCM = 0;
+    int fWIDE = 0, fKCM = 0, fEPL = 8;
     int64_t rowbytes = 0;
     size_t lds = 0;
     hipStream_t stream = nullptr;
@@ -143,21 +143,23 @@ em_status plan(em_ctx *c, size_t lds_max) {
     c->wide = false;
     c->fac = false;
     if (c->flags & EM_FLAG_FACTORED) {
-        int WIDE = 0, KCM = 0, BM = 0;
+        int WIDE = 0, KCM = 0, EPL = 8, BM = 0;
         size_t lds = 0;
         if (c->prec != P_F64 &&
-            fac_plan(c->prec, c->D, c->Q, c->K, c->Wp, lds_max, &WIDE, &KCM, &lds, &BM)) {
+            fac_plan(c->prec, c->D, c->Q, c->K, c->Wp, lds_max, &WIDE, &KCM, &EPL, &lds, &BM)) {
             c->fac = true;
             c->BM = BM;
             c->fWIDE = WIDE;
             c->fKCM = KCM;
+            c->fEPL = EPL;
             c->WM = 0;
             c->lds = lds;
             return EM_OK;
         }
         return fail(c, EM_EUNSUPPORTED,
-                    "the factored pass needs D = 512, Q a power-of-two multiple of 8 and a "
-                    "matrix-core precision");
+                    "the factored pass needs D = 512 with Q a power-of-two multiple of 8 and a "
+                    "matrix-core precision, or D = 2048 in fp16 / bf16 with Q a power-of-two "
+                    "multiple of 32");
     }
     const bool one_plane = c->prec == P_F16 || c->prec == P_BF16;
     if (one_plane && (c->flags & EM_FLAG_WIDE_PASS)) {
@@ -341,7 +343,7 @@ em_status run_pass(em_ctx *c, int flags, int64_t r0, int64_t r1, const double *a
     else if (c->wide)
         HIPCHK(c, launch_pass_wide(c->prec, c->wNTW, c->wUR, A, grid, c->lds, c->stream));
     else if (c->fac)
-        HIPCHK(c, launch_pass_fac(c->prec, c->fWIDE, c->fKCM, A, grid, c->lds, c->stream));
+        HIPCHK(c, launch_pass_fac(c->prec, c->fWIDE, c->fKCM, c->fEPL, A, grid, c->lds, c->stream));
     else
         HIPCHK(c, launch_pass(c->prec, c->BM, c->WM, c->LD, A, grid, c->lds, c->stream));
     if (ev) {
@@ -494,7 +496,7 @@ em_status em_init(em_ctx **out, const em_params *p, const void *obs_dev, const d
             occ = 1;
         }
     } else if (c->fac) {
-        if (pass_fac_setup(c->prec, c->fWIDE, c->fKCM, c->lds, &occ) != hipSuccess || occ < 1) {
+        if (pass_fac_setup(c->prec, c->fWIDE, c->fKCM, c->fEPL, c->lds, &occ) != hipSuccess || occ < 1) {
             (void)hipGetLastError();
             occ = 1;
         }
@@ -1081,7 +1083,7 @@ em_status em_get_info(const em_ctx *c, em_info *info) {
     std::snprintf(info->kernel, sizeof info->kernel, "%s",
                   c->ks     ? pass_ks_name(c->prec, c->BM, c->ksNT, c->ksKSS)
                   : c->wide ? pass_wide_name(c->prec, c->wNTW, c->wUR)
-                  : c->fac  ? pass_fac_name(c->prec, c->fWIDE, c->fKCM)
+                  : c->fac  ? pass_fac_name(c->prec, c->fWIDE, c->fKCM, c->fEPL)
                             : pass_kernel_name(c->prec, c->BM, c->WM, c->LD));
     return EM_OK;
 }

@@ -155,10 +155,10 @@ hipError_t launch_pass_wide(int prec, int NTW, int UR, const PassArgs &a, int gr
 hipError_t pass_wide_setup(int prec, int NTW, int UR, size_t lds, int *blocks_per_cu);
 const char *pass_wide_name(int prec, int NTW, int UR);
 bool fac_plan(int prec, int D, int Q, int K, int Wp, size_t lds_max, int *WIDE, int *KCM,
-              size_t *lds, int *BM);
-hipError_t launch_pass_fac(int prec, int WIDE, int KCM, const PassArgs &a, int grid, size_t lds,
-                           hipStream_t s);
-hipError_t pass_fac_setup(int prec, int WIDE, int KCM, size_t lds, int *blocks_per_cu);
-const char *pass_fac_name(int prec, int WIDE, int KCM);
+              int *EPL, size_t *lds, int *BM);
+hipError_t launch_pass_fac(int prec, int WIDE, int KCM, int EPL, const PassArgs &a, int grid,
+                           size_t lds, hipStream_t s);
+hipError_t pass_fac_setup(int prec, int WIDE, int KCM, int EPL, size_t lds, int *blocks_per_cu);
+const char *pass_fac_name(int prec, int WIDE, int KCM, int EPL);
 
 }  // namespace sem

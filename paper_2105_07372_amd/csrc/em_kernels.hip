@@ -1815,56 +1815,59 @@ __global__ __launch_bounds__(kThreads) void pass_wide_kernel(PassArgs A) {
 //   Re <v_j, R_{o_i} a> = Re sum_k c_jk exp(-i k theta_i),   c_jk = sum_q conj(v_jkq) a_kq.
 // Per row this costs 4D + 4KW flops instead of 4DW, no template exists, and the pass is a stream
 // over the rows.  Each wave owns fac_rpw rows of a tile of 8 fac_rpw rows and holds them in
-// registers (lane l: entries 8l .. 8l+7, so D = 512; Q/8 lanes share an angular frequency),
-// while the next tile's rows load.  c goes to LDS; C = [Re c | Im c] . [cos; sin] and
+// registers (lane l: entries EPL l .. EPL l + EPL - 1, so D = 64 EPL: EPL = 8 for D = 512, 32
+// for D = 2048 in one 16-bit plane; Q/EPL lanes share an angular frequency), while the next
+// tile's rows load.  c goes to LDS; C = [Re c | Im c] . [cos; sin] and
 // U = w [Re E | Im E] are FP32 matrix-core products against the phase table (fragments in
 // registers when Wp <= 64, streamed from L2 otherwise); the posteriors as in the other passes;
 // the M-step from the rows in registers, the eight waves' partial sums added in wave order into
-// per-entry FP64 accumulators.
+// per-entry FP64 accumulators (EPL = 8: the waves' FP32 partials summed by entry owners; EPL = 32:
+// the waves add theirs in wave order into an FP64 copy of S in LDS).
 
-// rows per wave per tile: 2 for the 16-word row formats (FP32, bf16x3), 4 for one 16-bit plane
-__host__ __device__ constexpr int fac_rpw(int prec) {
-    return (prec == P_F32 || prec == P_BF16X3) ? 2 : 4;
+// rows per wave per tile: 2 for the 16-word row formats (FP32, bf16x3) and for 32 entries per
+// lane, 4 for one 16-bit plane at 8 entries per lane
+__host__ __device__ constexpr int fac_rpw(int prec, int epl = 8) {
+    return (epl == 32 || prec == P_F32 || prec == P_BF16X3) ? 2 : 4;
 }
-constexpr int kFacEPL = 8;                    // entries per lane: D = 64 kFacEPL
 constexpr int kFacFlush = 4;                  // tiles summed in FP32 before the FP64 flush
+constexpr int kFacFlush32 = 8;                // ... with 32 entries per lane
 
 struct FacLds {
     int CBW, CSW, off_cs, off_u, off_sw, off_f, off_lr, off_a, total;
 };
-__host__ __device__ inline FacLds fac_lds(int K, int D, int Wp, int KCM, int BM) {
+__host__ __device__ inline FacLds fac_lds(int K, int D, int Wp, int KCM, int BM, int EPL = 8) {
     FacLds l;
     l.CBW = 4 * KCM + 4;                       // [Re c | Im c | 0 ..], conflict-free A reads
     l.CSW = (Wp > 64 ? Wp : 64) + 4;           // columns past Wp stay zero (register U path)
     l.off_cs = align_up(BM * l.CBW * 4, 16);
     l.off_u = align_up(l.off_cs + BM * l.CSW * 4, 16);
     l.off_sw = align_up(l.off_u + BM * K * 8, 16);
-    l.off_f = align_up(l.off_sw + 8 * (9 * D / 8) * 8, 16);
+    l.off_f = align_up(l.off_sw + (EPL == 32 ? D * 16 : 8 * (9 * D / 8) * 8), 16);
     l.off_lr = l.off_f + 2 * BM * 4;
     l.off_a = align_up(l.off_lr + Wp * 4, 16);
     l.total = l.off_a + D * 8;
     return l;
 }
 
-// Words of one stored row for lane l (entries 8l .. 8l+7): FP32 16 words (re, im per entry);
-// bf16x3 8 hi words then 8 lo words; fp16 / bf16 8 words.
-template <int P>
+// Words of one stored row for lane l (entries EPL l .. EPL l + EPL - 1): FP32 2 EPL words
+// (re, im per entry); bf16x3 EPL hi words then EPL lo words; fp16 / bf16 EPL words.
+template <int P, int EPL = 8>
 struct FacRow {
-    static constexpr int WPL = (P == P_F32 || P == P_BF16X3) ? 16 : 8;
+    static constexpr int WPL = (P == P_F32 || P == P_BF16X3) ? 2 * EPL : EPL;
     u32x4 w[WPL / 4];
     __device__ __forceinline__ void load(const uint8_t *row, int Dp, int lane) {
         if constexpr (P == P_F32) {
-            const u32x4 *p = (const u32x4 *)(row + 64 * lane);
+            const u32x4 *p = (const u32x4 *)(row + 8 * EPL * lane);
 #pragma unroll
-            for (int t = 0; t < 4; ++t) w[t] = p[t];
+            for (int t = 0; t < WPL / 4; ++t) w[t] = p[t];
         } else {
-            const u32x4 *p = (const u32x4 *)(row + 32 * lane);
-            w[0] = p[0];
-            w[1] = p[1];
+            const u32x4 *p = (const u32x4 *)(row + 4 * EPL * lane);
+#pragma unroll
+            for (int t = 0; t < EPL / 4; ++t) w[t] = p[t];
             if constexpr (P == P_BF16X3) {
-                const u32x4 *q = (const u32x4 *)(row + 2 * Dp + 32 * lane);
-                w[2] = q[0];
-                w[3] = q[1];
+                const u32x4 *q = (const u32x4 *)(row + 2 * Dp + 4 * EPL * lane);
+#pragma unroll
+                for (int t = 0; t < EPL / 4; ++t) w[EPL / 4 + t] = q[t];
             }
         }
     }
@@ -1880,7 +1883,7 @@ struct FacRow {
             const uint32_t x = w[e >> 2][e & 3];
             float re = __uint_as_float(x << 16), im = __uint_as_float(x & 0xffff0000u);
             if constexpr (P == P_BF16X3) {
-                const uint32_t y = w[2 + (e >> 2)][e & 3];
+                const uint32_t y = w[EPL / 4 + (e >> 2)][e & 3];
                 re += __uint_as_float(y << 16);
                 im += __uint_as_float(y & 0xffff0000u);
             }
@@ -1890,11 +1893,13 @@ struct FacRow {
 };
 
 // WIDE = 0: Wp <= 64 (phase fragments in registers); 1: longer windows.  KCM = k-steps of 4
-// columns over [Re c | Im c] (2K <= 4 KCM).
-template <int P, int WIDE, int KCM>
+// columns over [Re c | Im c] (2K <= 4 KCM).  EPL = entries per lane (D = 64 EPL).
+template <int P, int WIDE, int KCM, int EPL>
 __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
     static_assert(P != P_F64, "matrix-core precisions");
-    constexpr int RPW = fac_rpw(P), BM = 8 * RPW, EPL = kFacEPL, DPT = 1;   // D = 512 = threads
+    static_assert(EPL == 8 || (EPL == 32 && WIDE && (P == P_F16 || P == P_BF16)),
+                  "32 entries per lane: one 16-bit plane, phase fragments from L2");
+    constexpr int RPW = fac_rpw(P, EPL), BM = 8 * RPW, DPT = 64 * EPL / kThreads;
     if ((A.flags & PF_CHECK_STOP) && *A.stopped) return;
 
     extern __shared__ __align__(16) uint8_t smem[];
@@ -1902,7 +1907,7 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int g = lane >> 4, c = lane & 15;
     const int K = A.K, D = A.D, Wp = A.Wp, NT = Wp / 16;
-    const FacLds LY = fac_lds(K, D, Wp, KCM, BM);
+    const FacLds LY = fac_lds(K, D, Wp, KCM, BM, EPL);
     float *cb = (float *)smem;
     float *Cs = (float *)(smem + LY.off_cs);
     float2 *Us = (float2 *)(smem + LY.off_u);
@@ -1916,6 +1921,8 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
     for (int i = tid; i < Wp; i += kThreads) lrs[i] = A.logrho32[i];
     for (int d = tid; d < D; d += kThreads)
         as[(d % EPL) * 64 + d / EPL] = make_float2((float)A.a[2 * d], (float)A.a[2 * d + 1]);
+    if constexpr (EPL == 32)
+        for (int d = tid; d < D; d += kThreads) ((double2 *)Sw)[d] = make_double2(0.0, 0.0);
 
     // this lane's entries and their coefficients a (FP32), its angular frequency and lane group
     const int d0 = EPL * lane;
@@ -1947,7 +1954,7 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
     PassAcc<DPT> acc;
     acc.init();
     const int64_t ntiles = (A.row_end - A.row_begin + BM - 1) / BM;
-    FacRow<P> vn[RPW];
+    FacRow<P, EPL> vn[RPW];
     float rsn[RPW];
     auto load_tile = [&](int64_t t) {
         const int64_t rb = A.row_begin + t * BM + RPW * wave;
@@ -1963,6 +1970,21 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
     for (int e = 0; e < EPL; ++e) sr[e] = si[e] = 0.f;
     int nacc = 0;
     auto flush = [&]() {
+      if constexpr (EPL == 32) {
+        // the eight waves add their FP32 partials into the FP64 copy of S in wave order
+        double2 *Sd = (double2 *)Sw;
+        for (int w = 0; w < 8; ++w) {
+            if (wave == w)
+#pragma unroll
+                for (int e = 0; e < EPL; ++e) {
+                    double2 t = Sd[EPL * lane + e];
+                    t.x += (double)sr[e];
+                    t.y += (double)si[e];
+                    Sd[EPL * lane + e] = t;
+                }
+            lds_barrier();
+        }
+      } else {
         // wave w's partials at [w][9 (d / 8) + d % 8] (padded: the lanes' writes spread over
         // the banks)
         const int SWS = 9 * D / 8;
@@ -1985,23 +2007,28 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
                 acc.S[cc].y += (double)s.y;
             }
         }
+      }
 #pragma unroll
         for (int e = 0; e < EPL; ++e) sr[e] = si[e] = 0.f;
         nacc = 0;
     };
     int64_t tile = blockIdx.x;
-    if (tile < ntiles) load_tile(tile);
+    // EPL = 8: the next tile's rows load into registers while this one is used; EPL = 32 (rows of
+    // 32 words per lane) loads each tile at its start, the register file holding one tile
+    constexpr bool kPrefetch = EPL == 8;
+    if (kPrefetch && tile < ntiles) load_tile(tile);
     for (; tile < ntiles; tile += gridDim.x) {
         const int64_t r0 = A.row_begin + tile * BM;
         const int rows = (int)((A.row_end - r0) < BM ? (A.row_end - r0) : BM);
-        FacRow<P> vc[RPW];
+        if constexpr (!kPrefetch) load_tile(tile);
+        FacRow<P, EPL> vc[RPW];
         float rsc[RPW];
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
             vc[r] = vn[r];
             rsc[r] = rsn[r];
         }
-        if (tile + gridDim.x < ntiles) load_tile(tile + gridDim.x);
+        if (kPrefetch && tile + gridDim.x < ntiles) load_tile(tile + gridDim.x);
 
         // ---- c_jk for this wave's rows; row factors
 #pragma unroll
@@ -2010,6 +2037,8 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
             float cr = 0.f, ci = 0.f;
 #pragma unroll
             for (int e = 0; e < EPL; ++e) {
+                // (32 entries per lane: the coefficient reads in groups of 8, not all at once)
+                if (EPL == 32 && e % 8 == 0) asm volatile("" ::: "memory");
                 const float2 v = vc[r].entry(e);
                 const float2 av = as[e * 64 + lane];
                 cr += v.x * av.x + v.y * av.y;            // Re conj(v) a
@@ -2054,7 +2083,7 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
                 const int m = p % MT, n = p / MT;
                 f32x4 cacc = (f32x4){0.f, 0.f, 0.f, 0.f};
                 const float *eb = A.E2 + (int64_t)(16 * n + c) * 2 * K;
-#pragma unroll
+#pragma unroll(EPL == 32 ? 8 : KCM)
                 for (int kk = 0; kk < KCM; ++kk) {
                     const int colk = 4 * kk + g;
                     const float b = colk < 2 * K ? eb[colk] : 0.f;
@@ -2094,9 +2123,17 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
                 si[e] += u.x * v.y + u.y * v.x;
             }
         }
-        if (++nacc == kFacFlush || tile + gridDim.x >= ntiles) flush();
+        if (++nacc == (EPL == 32 ? kFacFlush32 : kFacFlush) || tile + gridDim.x >= ntiles) flush();
     }
     __syncthreads();
+    if constexpr (EPL == 32) {
+#pragma unroll
+        for (int cc = 0; cc < DPT; ++cc) {
+            const int d = tid + cc * kThreads;
+            if (d < D) acc.S[cc] = ((const double2 *)Sw)[d];
+        }
+        __syncthreads();
+    }
     if (A.partials) write_partials(A, acc, smem);
 }
 
@@ -2641,46 +2678,52 @@ const char *pass_wide_name(int prec, int NTW, int UR) {
 
 // Factored variants: (precision, window > 64, k-steps over [Re c | Im c]).
 #define SEM_FAC_VARIANTS(X)                                                                    \
-    X(P_F32, 0, 16) X(P_F32, 1, 16) X(P_F32, 0, 32) X(P_F32, 1, 32)                             \
-    X(P_BF16X3, 0, 16) X(P_BF16X3, 1, 16) X(P_BF16X3, 0, 32) X(P_BF16X3, 1, 32)                 \
-    X(P_F16, 0, 16) X(P_F16, 1, 16) X(P_F16, 0, 32) X(P_F16, 1, 32)                             \
-    X(P_BF16, 0, 16) X(P_BF16, 1, 16) X(P_BF16, 0, 32) X(P_BF16, 1, 32)
+    X(P_F32, 0, 16, 8) X(P_F32, 1, 16, 8) X(P_F32, 0, 32, 8) X(P_F32, 1, 32, 8)                 \
+    X(P_BF16X3, 0, 16, 8) X(P_BF16X3, 1, 16, 8) X(P_BF16X3, 0, 32, 8) X(P_BF16X3, 1, 32, 8)     \
+    X(P_F16, 0, 16, 8) X(P_F16, 1, 16, 8) X(P_F16, 0, 32, 8) X(P_F16, 1, 32, 8)                 \
+    X(P_BF16, 0, 16, 8) X(P_BF16, 1, 16, 8) X(P_BF16, 0, 32, 8) X(P_BF16, 1, 32, 8)             \
+    X(P_F16, 1, 16, 32) X(P_F16, 1, 32, 32) X(P_BF16, 1, 16, 32) X(P_BF16, 1, 32, 32)
 
-static pass_fn find_fac(int prec, int WIDE, int KCM) {
-#define SEM_X(P, Wd, KC)                                                                       \
-    if (prec == P && WIDE == Wd && KCM == KC) return pass_fac_kernel<P, Wd, KC>;
+static pass_fn find_fac(int prec, int WIDE, int KCM, int EPL) {
+#define SEM_X(P, Wd, KC, E)                                                                    \
+    if (prec == P && WIDE == Wd && KCM == KC && EPL == E) return pass_fac_kernel<P, Wd, KC, E>;
     SEM_FAC_VARIANTS(SEM_X)
 #undef SEM_X
     return nullptr;
 }
 
 bool fac_plan(int prec, int D, int Q, int K, int Wp, size_t lds_max, int *WIDE, int *KCM,
-              size_t *lds, int *BM) {
-    if (D != 64 * kFacEPL || Q % kFacEPL != 0) return false;
-    const int lpk = Q / kFacEPL;
+              int *EPL, size_t *lds, int *BM) {
+    int epl = 0;
+    if (D == 512 && Q % 8 == 0) epl = 8;
+    else if (D == 2048 && (prec == P_F16 || prec == P_BF16) && Q % 32 == 0) epl = 32;
+    else return false;
+    const int lpk = Q / epl;
     if (lpk & (lpk - 1)) return false;                       // lanes per frequency: 2^n
     const int kcm = 2 * K <= 64 ? 16 : (2 * K <= 128 ? 32 : 0);
-    const int wide = Wp > 64 ? 1 : 0;
-    if (!kcm || !find_fac(prec, wide, kcm)) return false;
-    const size_t b = (size_t)fac_lds(K, D, Wp, kcm, 8 * fac_rpw(prec)).total;
+    const int wide = (epl == 32 || Wp > 64) ? 1 : 0;
+    if (!kcm || !find_fac(prec, wide, kcm, epl)) return false;
+    const int bm = 8 * fac_rpw(prec, epl);
+    const size_t b = (size_t)fac_lds(K, D, Wp, kcm, bm, epl).total;
     if (b > lds_max) return false;
     *WIDE = wide;
     *KCM = kcm;
+    *EPL = epl;
     *lds = b;
-    *BM = 8 * fac_rpw(prec);
+    *BM = bm;
     return true;
 }
 
-hipError_t launch_pass_fac(int prec, int WIDE, int KCM, const PassArgs &a, int grid, size_t lds,
-                           hipStream_t s) {
-    pass_fn f = find_fac(prec, WIDE, KCM);
+hipError_t launch_pass_fac(int prec, int WIDE, int KCM, int EPL, const PassArgs &a, int grid,
+                           size_t lds, hipStream_t s) {
+    pass_fn f = find_fac(prec, WIDE, KCM, EPL);
     if (!f) return hipErrorInvalidValue;
     hipLaunchKernelGGL(f, dim3(grid), dim3(kThreads), lds, s, a);
     return hipGetLastError();
 }
 
-hipError_t pass_fac_setup(int prec, int WIDE, int KCM, size_t lds, int *blocks_per_cu) {
-    pass_fn f = find_fac(prec, WIDE, KCM);
+hipError_t pass_fac_setup(int prec, int WIDE, int KCM, int EPL, size_t lds, int *blocks_per_cu) {
+    pass_fn f = find_fac(prec, WIDE, KCM, EPL);
     if (!f) return hipErrorInvalidValue;
     hipError_t e = hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
@@ -2689,11 +2732,10 @@ hipError_t pass_fac_setup(int prec, int WIDE, int KCM, size_t lds, int *blocks_p
                                                         lds);
 }
 
-const char *pass_fac_name(int prec, int WIDE, int KCM) {
+const char *pass_fac_name(int prec, int WIDE, int KCM, int EPL) {
     static char buf[64];
-    snprintf(buf, sizeof buf, "pass_fac_kernel<%s,BM=%d,%s,KC=%d>", kPrecName[prec],
-             8 * fac_rpw(prec),
-             WIDE ? "L2" : "reg", KCM);
+    snprintf(buf, sizeof buf, "pass_fac_kernel<%s,BM=%d,%s,KC=%d%s>", kPrecName[prec],
+             8 * fac_rpw(prec, EPL), WIDE ? "L2" : "reg", KCM, EPL == 32 ? ",E32" : "");
     return buf;
 }
 

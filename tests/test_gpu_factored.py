@@ -1,7 +1,8 @@
 """The factored E(+M) pass (correlations through the per-frequency sums c_jk, an exact rewrite of
 the contraction; no template) against the FP64 oracle: teacher-forced steps on windowed and
 full-search shapes with one, two and four lanes per angular frequency and ragged row tails, every
-precision it supports; a windowed trajectory; the posterior queries and the adjoint."""
+precision it supports; the large-image shape (D = 2048, 32 entries per lane, fp16 and bf16),
+including its full size; a windowed trajectory; the posterior queries and the adjoint."""
 import numpy as np
 import pytest
 
@@ -134,3 +135,101 @@ def test_factored_rejects_unsupported_shapes(gpu):
         EM(torch.from_numpy(V).to(gpu), K=8, Q=6, L=12, sigma2=1.0, precision="fp32",
            factored=True)
     assert ei.value.status == -6
+
+
+SHAPES2048 = {
+    # name: (K, Q, L, half window, N): 32 entries per lane, D = 2048
+    "c5": (64, 32, 720, 90, 3001),         # the large-image shape, W = 181
+    "c5narrow": (64, 32, 720, 45, 1001),   # W = 91
+    "q64": (32, 64, 360, 24, 777),         # two lanes per frequency, 2K = 64, W = 49
+}
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("shape", list(SHAPES2048))
+def test_factored_2048_teacher_forced_step(gpu, prec, shape):
+    import torch
+    from paper_2105_07372_amd import EM
+    K, Q, L, h, N = SHAPES2048[shape]
+    w = wl.WORKLOADS["c5"].replace(K=K, Q=Q, L=L, N=N, half_window=h)
+    a_true = wl.image(w, 0)
+    V = wl.observations(w, 0, a=a_true)
+    s2 = wl.noise_variance(a_true, w.snr)
+    lo, W = w.window
+    rb, _, _ = oracle.histogram_prior(wl.prior_error_draws(w, 0, 200_000), w.L, lo, W)
+    rng = np.random.default_rng(6)
+    a_t = V.mean(axis=0) + 0.1 * a_true * rng.standard_normal(w.D)
+    rho_t = rb * rng.uniform(0.5, 1.5, W)
+    rho_t /= rho_t.sum()
+    print(f"factored D=2048 shape={shape} prec={prec} N={N} W={W}", flush=True)
+    em = EM(torch.from_numpy(V.astype(np.complex64)).to(gpu), K=K, Q=Q, L=L, sigma2=s2,
+            window=(lo, W), prior=rb, gamma=50.0, precision=prec, factored=True)
+    assert em.info()["kernel"].startswith("pass_fac_kernel") and "E32" in em.info()["kernel"]
+    em.set_state(a_t, rho_t, 0)
+    offs = oracle.offsets(lo, W)
+    wg, am, mg = em.posterior()
+    wo, _, _ = oracle.estep(V, a_t, rho_t, s2, w.kbar, L, offs)
+    ao, mo = oracle.argmax_margin(wo)
+    wg, am = wg.cpu().numpy().astype(np.float64), am.cpu().numpy()
+    assert np.abs(wg - wo).max() <= TOL[prec]["post"]
+    assert np.linalg.norm(wg - wo) / np.linalg.norm(wo) <= TOL[prec]["post"]
+    sure = mo > (1e-2 if prec == "bf16" else 1e-3)
+    assert int(np.sum(am[sure] != ao[sure])) == 0
+    ll_ref = oracle.loglik(V, a_t, rho_t, s2, w.kbar, L, offs)
+    assert abs(em.loglik() - ll_ref) <= TOL[prec]["ll"] * abs(ll_ref)
+    em.step(1)
+    it = oracle.em_iteration(V, a_t, rho_t, s2, w.kbar, L, offs, rho_bar=rb, gamma=50.0)
+    a1, rho1, _ = em.state()
+    assert np.linalg.norm(a1 - it["a"]) / np.linalg.norm(it["a"]) <= TOL[prec]["a"]
+    assert np.abs(rho1 - it["rho"]).max() <= TOL[prec]["a"]
+    em.close()
+
+
+@pytest.mark.timeout(900)
+def test_factored_2048_full_size(gpu):
+    """N = 10^6, D = 2048, L = 720, W = 181, fp16, factored: sampled rows' posteriors against the
+    oracle, one EM step against the M-step and distribution update evaluated in FP64 from the
+    kernel's own posteriors over all rows, and the pass time."""
+    import torch
+    from paper_2105_07372_amd import EM
+    w = wl.WORKLOADS["c5"]
+    a_true = wl.image(w, 0)
+    s2 = wl.noise_variance(a_true, w.snr)
+    lo, W = w.window
+    rb, _, _ = oracle.histogram_prior(wl.prior_error_draws(w, 0), w.L, lo, W)
+    obs = torch.empty((w.N, w.D), dtype=torch.complex64, device=gpu)
+    for r0, ch in wl.observation_chunks(w, 0, dtype=np.complex64, a=a_true, workers=16):
+        obs[r0:r0 + len(ch)].copy_(torch.from_numpy(ch))
+    print("factored full size: generated", flush=True)
+    rng = np.random.default_rng(11)
+    a_t = 0.9 * a_true + 0.05 * np.sqrt(s2) * (rng.standard_normal(w.D) + 1j * rng.standard_normal(w.D))
+    em = EM(obs, K=w.K, Q=w.Q, L=w.L, sigma2=s2, window=(lo, W), prior=rb, gamma=w.gamma,
+            precision="fp16", timing=True, factored=True)
+    assert "E32" in em.info()["kernel"], em.info()
+    em.set_state(a_t, rb, 0)
+    offs = oracle.offsets(lo, W)
+    for (r0, n) in ((0, 512), (w.N - 512, 512)):
+        Vs = wl.observations(w, 0, r0, r0 + n, dtype=np.complex64, a=a_true).astype(np.complex128)
+        wg, am, _ = em.posterior(r0, n)
+        wo, _, _ = oracle.estep(Vs, a_t, rb, s2, w.kbar, w.L, offs)
+        assert np.abs(wg.cpu().numpy().astype(np.float64) - wo).max() <= TOL["fp16"]["post"]
+    E = torch.from_numpy(np.exp(1j * 2 * np.pi * np.outer(offs, w.kbar) / w.L)).to(gpu)
+    Z = torch.zeros((W, w.D), dtype=torch.complex128, device=gpu)
+    Wsum = torch.zeros(W, dtype=torch.float64, device=gpu)
+    for r0 in range(0, w.N, 65536):
+        n = min(65536, w.N - r0)
+        Pm, _, _ = em.posterior(r0, n)
+        P64 = Pm.to(torch.float64)
+        Wsum += P64.sum(dim=0)
+        Z += P64.to(torch.complex128).t().contiguous() @ obs[r0:r0 + n].to(torch.complex128)
+    a_ref = ((E * Z).sum(dim=0) / w.N).cpu().numpy()
+    wt = Wsum.cpu().numpy() + w.gamma * rb
+    em.step(1)
+    a1, rho1, _ = em.state()
+    assert np.linalg.norm(a1 - a_ref) / np.linalg.norm(a_ref) <= 1e-5
+    assert np.abs(rho1 - wt / wt.sum()).max() <= 1e-6
+    em.pass_time(reset=True)
+    em.step(3)
+    ms, n = em.pass_time(reset=True)
+    print(f"factored full size: {em.info()['kernel']} {1e3 * ms / n:.1f} us per pass", flush=True)
+    em.close()
