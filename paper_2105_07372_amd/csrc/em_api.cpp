@@ -44,6 +44,7 @@ struct em_ctx {
     int wNTW = 0, wUR = 0;
     bool fac = false;     // factored pass (per-frequency sums; no template)
     int fWIDE = 0, fKCM = 0, fEPL = 8;
+    bool has_angles = false;   // the window is an explicit angle list (em_params.angles)
     int64_t rowbytes = 0;
     size_t lds = 0;
     hipStream_t stream = nullptr;
@@ -146,7 +147,8 @@ em_status plan(em_ctx *c, size_t lds_max) {
         int WIDE = 0, KCM = 0, EPL = 8, BM = 0;
         size_t lds = 0;
         if (c->prec != P_F64 &&
-            fac_plan(c->prec, c->D, c->Q, c->K, c->Wp, lds_max, &WIDE, &KCM, &EPL, &lds, &BM)) {
+            fac_plan(c->prec, c->D, c->Q, c->K, c->Wp, c->has_angles ? 0 : c->L, lds_max, &WIDE,
+                     &KCM, &EPL, &lds, &BM)) {
             c->fac = true;
             c->BM = BM;
             c->fWIDE = WIDE;
@@ -316,6 +318,10 @@ em_status run_pass(em_ctx *c, int flags, int64_t r0, int64_t r1, const double *a
     A.logrho64 = lr64;
     A.E2 = c->E2;
     A.E64 = c->E64;
+    A.phase = c->phase;
+    A.L = c->L;
+    A.lo = c->lo;
+    A.grid = c->has_angles ? 0 : 1;
     A.row_begin = r0;
     A.row_end = r1;
     A.D = c->D;
@@ -450,6 +456,7 @@ em_status em_init(em_ctx **out, const em_params *p, const void *obs_dev, const d
     c->L = p->L;
     c->lo = ((p->window_lo % p->L) + p->L) % p->L;
     c->W = p->window_count;
+    c->has_angles = p->angles != nullptr;
     c->Wp = (c->W + 15) / 16 * 16;
     c->sigma2 = p->sigma2;
     c->gamma = p->gamma;

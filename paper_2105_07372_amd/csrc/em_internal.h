@@ -50,6 +50,8 @@ struct PassArgs {
     const double *logrho64;
     const float *E2;           // Wp x 2K: [Re exp(+i k theta_i) | Im ...] (zero rows on padding)
     const double2 *E64;        // Wp x K: exp(+i k theta_i), FP64 path
+    const double2 *phase;      // L: exp(+2 pi i m / L) (grid windows: E[i, k] = phase[k o_i mod L])
+    int L, lo, grid;           // grid: the window is the offsets lo .. lo + W - 1 (no angle list)
     int64_t row_begin, row_end;
     int D, K, Q, Dp, W, Wp;
     double coef;               // 2 / sigma^2
@@ -154,8 +156,9 @@ hipError_t launch_pass_wide(int prec, int NTW, int UR, const PassArgs &a, int gr
                             hipStream_t s);
 hipError_t pass_wide_setup(int prec, int NTW, int UR, size_t lds, int *blocks_per_cu);
 const char *pass_wide_name(int prec, int NTW, int UR);
-bool fac_plan(int prec, int D, int Q, int K, int Wp, size_t lds_max, int *WIDE, int *KCM,
-              int *EPL, size_t *lds, int *BM);
+// gridL: L for a grid window (its phase table may be staged in LDS), 0 for an angle list
+bool fac_plan(int prec, int D, int Q, int K, int Wp, int gridL, size_t lds_max, int *WIDE,
+              int *KCM, int *EPL, size_t *lds, int *BM);
 hipError_t launch_pass_fac(int prec, int WIDE, int KCM, int EPL, const PassArgs &a, int grid,
                            size_t lds, hipStream_t s);
 hipError_t pass_fac_setup(int prec, int WIDE, int KCM, int EPL, size_t lds, int *blocks_per_cu);

@@ -1832,10 +1832,14 @@ __host__ __device__ constexpr int fac_rpw(int prec, int epl = 8) {
 constexpr int kFacFlush = 4;                  // tiles summed in FP32 before the FP64 flush
 constexpr int kFacFlush32 = 8;                // ... with 32 entries per lane
 
+constexpr int kFacPhLds = 2048;               // grid phase table staged in LDS up to this L
+
 struct FacLds {
-    int CBW, CSW, off_cs, off_u, off_sw, off_f, off_lr, off_a, total;
+    int CBW, CSW, off_cs, off_u, off_sw, off_f, off_lr, off_a, off_ph, total;
 };
-__host__ __device__ inline FacLds fac_lds(int K, int D, int Wp, int KCM, int BM, int EPL = 8) {
+// PHL: entries of the grid phase table kept in LDS (0: none)
+__host__ __device__ inline FacLds fac_lds(int K, int D, int Wp, int KCM, int BM, int EPL = 8,
+                                          int PHL = 0) {
     FacLds l;
     l.CBW = 4 * KCM + 4;                       // [Re c | Im c | 0 ..], conflict-free A reads
     l.CSW = (Wp > 64 ? Wp : 64) + 4;           // columns past Wp stay zero (register U path)
@@ -1845,8 +1849,94 @@ __host__ __device__ inline FacLds fac_lds(int K, int D, int Wp, int KCM, int BM,
     l.off_f = align_up(l.off_sw + (EPL == 32 ? D * 16 : 8 * (9 * D / 8) * 8), 16);
     l.off_lr = l.off_f + 2 * BM * 4;
     l.off_a = align_up(l.off_lr + Wp * 4, 16);
-    l.total = l.off_a + D * 8;
+    l.off_ph = align_up(l.off_a + D * 8, 16);
+    l.total = l.off_ph + PHL * 8;
     return l;
+}
+
+// The factored pass's C and U products with the phase factors read from the grid phase table in
+// LDS (ph[m] = (cos, sin)(2 pi m / L), E[i, k] = ph[(k (lo + i)) mod L]) instead of the E2 table
+// in L2.  C: wave w takes the column tiles w, w + 8, .. of the BM x Wp tile.
+template <int BM, int KCM>
+__device__ __forceinline__ void fac_c_ph(const float *cb, int CBW, const float2 *ph, int L, int lo,
+                                         int W, int NT, int K, const float *rowf,
+                                         const float *lrs, float *Cs, int CSW) {
+    constexpr int MT = BM / 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
+    for (int p = wave; p < MT * NT; p += 8) {
+        const int m = p % MT, n = p / MT;
+        const int i = 16 * n + c;
+        const int mo = i < W ? (lo + i) % L : 0;
+        f32x4 cacc = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll 8
+        for (int kk = 0; kk < KCM; ++kk) {
+            const int colk = 4 * kk + g;
+            float b = 0.f;
+            if (i < W && colk < 2 * K) {
+                const int kq = colk < K ? colk : colk - K;
+                const float2 e = ph[(kq * mo) % L];
+                b = colk < K ? e.x : e.y;
+            }
+            const float a = cb[(16 * m + c) * CBW + colk];
+            cacc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, cacc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int row = 16 * m + 4 * g + q;
+            Cs[row * CSW + i] = cacc[q] * rowf[row] + lrs[i];
+        }
+    }
+}
+
+// U (BM x 2K) = w (BM x Wp) . [Re E | Im E] with E from the LDS grid phase table; wave w takes
+// the 16-column tiles w, w + 8, .. of U; lane (g, rl) steps its window index i = 4 kk + g, so
+// its phase index moves by 4 k (mod L) per step.
+template <int BM>
+__device__ __forceinline__ void u_mfma_ph(const float *Cs, int CSW, const float2 *ph, int L,
+                                          int lo, int W, int Wp, int K, const float *rowu,
+                                          float2 *Us) {
+    constexpr int MS = BM / 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, rl = lane & 15;
+    const int NTU = (2 * K + 15) / 16, KG = Wp / 4;
+    for (int nt = wave; nt < NTU; nt += kThreads / 64) {
+        f32x4 acc[MS];
+#pragma unroll
+        for (int m = 0; m < MS; ++m) acc[m] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        const int col = nt * 16 + rl;
+        const bool cok = col < 2 * K;
+        const int kq = col < K ? col : col - K;
+        const bool im = col >= K;
+        int mi = cok ? (int)(((int64_t)kq * ((lo + g) % L)) % L) : 0;
+        const int step = cok ? (4 * kq) % L : 0;
+        for (int kk = 0; kk < KG; ++kk) {
+            const int i = 4 * kk + g;
+            float b = 0.f;
+            if (cok && i < W) {
+                const float2 e = ph[mi];
+                b = im ? e.y : e.x;
+            }
+            mi += step;
+            if (mi >= L) mi -= L;
+#pragma unroll
+            for (int m = 0; m < MS; ++m) {
+                const float a = Cs[(m * 16 + rl) * CSW + kk * 4 + g];
+                acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[m], 0, 0, 0);
+            }
+        }
+        if (cok) {
+#pragma unroll
+            for (int m = 0; m < MS; ++m)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row = m * 16 + 4 * g + q;
+                    const float v = acc[m][q] * rowu[row];
+                    if (col < K)
+                        Us[row * K + col].x = v;
+                    else
+                        Us[row * K + col - K].y = v;
+                }
+        }
+    }
 }
 
 // Words of one stored row for lane l (entries EPL l .. EPL l + EPL - 1): FP32 2 EPL words
@@ -1907,7 +1997,13 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int g = lane >> 4, c = lane & 15;
     const int K = A.K, D = A.D, Wp = A.Wp, NT = Wp / 16;
-    const FacLds LY = fac_lds(K, D, Wp, KCM, BM, EPL);
+    // long windows on the grid: the phase factors come from an LDS copy of the grid phase table
+    const bool use_ph = WIDE && A.grid && A.L <= kFacPhLds;
+    const FacLds LY = fac_lds(K, D, Wp, KCM, BM, EPL, use_ph ? A.L : 0);
+    float2 *phs = (float2 *)(smem + LY.off_ph);
+    if (use_ph)
+        for (int m = tid; m < A.L; m += kThreads)
+            phs[m] = make_float2((float)A.phase[m].x, (float)A.phase[m].y);
     float *cb = (float *)smem;
     float *Cs = (float *)(smem + LY.off_cs);
     float2 *Us = (float2 *)(smem + LY.off_u);
@@ -2077,6 +2173,8 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
                 Cs[row * LY.CSW + col] = cn < NT ? cacc[q] * rowf[row] + lrs[col] : 0.f;
             }
           }
+        } else if (use_ph) {
+            fac_c_ph<BM, KCM>(cb, LY.CBW, phs, A.L, A.lo, A.W, NT, K, rowf, lrs, Cs, LY.CSW);
         } else {
             constexpr int MT = BM / 16;
             for (int p = wave; p < MT * NT; p += 8) {
@@ -2108,7 +2206,10 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
         if constexpr (!WIDE)
             u_wide_reg<BM, 16>(Cs, LY.CSW, ereg, K, rowu, Us, ucol);
         else
-            u_mfma<BM>(Cs, LY.CSW, A.E2, Wp, K, rowu, Us);
+            if (use_ph)
+                u_mfma_ph<BM>(Cs, LY.CSW, phs, A.L, A.lo, A.W, Wp, K, rowu, Us);
+            else
+                u_mfma<BM>(Cs, LY.CSW, A.E2, Wp, K, rowu, Us);
         lds_barrier();
         // M-step from the rows in registers: this lane's entries over this wave's rows, summed
         // in FP32 over kFacFlush tiles, then the eight waves' partials in wave order into FP64
@@ -2692,8 +2793,8 @@ static pass_fn find_fac(int prec, int WIDE, int KCM, int EPL) {
     return nullptr;
 }
 
-bool fac_plan(int prec, int D, int Q, int K, int Wp, size_t lds_max, int *WIDE, int *KCM,
-              int *EPL, size_t *lds, int *BM) {
+bool fac_plan(int prec, int D, int Q, int K, int Wp, int gridL, size_t lds_max, int *WIDE,
+              int *KCM, int *EPL, size_t *lds, int *BM) {
     int epl = 0;
     if (D == 512 && Q % 8 == 0) epl = 8;
     else if (D == 2048 && (prec == P_F16 || prec == P_BF16) && Q % 32 == 0) epl = 32;
@@ -2704,7 +2805,8 @@ bool fac_plan(int prec, int D, int Q, int K, int Wp, size_t lds_max, int *WIDE, 
     const int wide = (epl == 32 || Wp > 64) ? 1 : 0;
     if (!kcm || !find_fac(prec, wide, kcm, epl)) return false;
     const int bm = 8 * fac_rpw(prec, epl);
-    const size_t b = (size_t)fac_lds(K, D, Wp, kcm, bm, epl).total;
+    const int phl = (wide && gridL > 0 && gridL <= kFacPhLds) ? gridL : 0;
+    const size_t b = (size_t)fac_lds(K, D, Wp, kcm, bm, epl, phl).total;
     if (b > lds_max) return false;
     *WIDE = wide;
     *KCM = kcm;
