@@ -313,6 +313,8 @@ def relative_rotations(obs, K: int, Q: int, L: int, P: Optional[int] = None, str
     dot [P, P]) as CUDA tensors (em_relative_rotations)."""
     import torch
     P = int(obs.shape[0]) if P is None else int(P)
+    if not 2 <= P <= int(obs.shape[0]):
+        raise ValueError("P must be in [2, number of rows of obs]")
     rel = torch.empty((P, P), dtype=torch.int32, device=obs.device)
     gap = torch.empty((P, P), dtype=torch.float32, device=obs.device)
     dot = torch.empty((P, P), dtype=torch.float32, device=obs.device)
