@@ -10,7 +10,7 @@ plain full-search FP32 EM (all 360 rotations, uniform prior) on the same observa
 windowed variant, the factored E-step (per-frequency sums, an exact rewrite of the correlation:
 windowed FP32 / fp16 and full search FP32), and the FP64 CPU oracle on the host cores.
 
-Prints one JSON line.  --gpus N with N > 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus N with N > 1 is refused: the path runs on one GPU.
 """
 from __future__ import annotations
 
@@ -112,7 +112,7 @@ def main():
                          "byte counters of a profiler run) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the path runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU form would split the observations and all-reduce the FP64 "
               "M-step partials once per iteration)", file=sys.stderr)
         sys.exit(2)

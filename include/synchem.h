@@ -41,7 +41,7 @@ typedef enum {
     EM_EDEVICE = -3,         /* a HIP runtime call failed                                   */
     EM_ESTATE = -4,          /* call not valid in the context's state (e.g. bwd before fwd) */
     EM_ENONFINITE = -5,      /* the observations contain NaN or Inf                         */
-    EM_EUNSUPPORTED = -6     /* valid but outside this build's limits (see em_params)       */
+    EM_EUNSUPPORTED = -6     /* valid but outside the library's limits (see em_params)      */
 } em_status;
 
 /* Arithmetic of the observation x template correlation (the E-step contraction).  Every mode

@@ -230,7 +230,7 @@ em_status plan(em_ctx *c, size_t lds_max) {
     }
     if (!c->BM)
         return fail(c, EM_EUNSUPPORTED,
-                    "no E+M pass of this build fits rows of " + std::to_string(c->rowbytes) +
+                    "no E+M pass fits rows of " + std::to_string(c->rowbytes) +
                         " bytes with this window");
     return EM_OK;
 }
