@@ -67,7 +67,7 @@ typedef enum { EM_FP64 = 0, EM_FP32 = 1, EM_BF16X3 = 2, EM_FP16 = 3, EM_BF16 = 4
                                            (3), that needs no template); D = 512 with Q a power-
                                            of-two multiple of 8 (any precision but EM_FP64), or
                                            D = 2048 in EM_FP16 / EM_BF16 with Q a power-of-two
-                                           multiple of 32; else EM_EUNSUPPORTED */
+                                           multiple of 16; else EM_EUNSUPPORTED */
 
 typedef struct {
     int64_t n_obs;          /* N >= 1                                                        */

@@ -161,7 +161,7 @@ em_status plan(em_ctx *c, size_t lds_max) {
         return fail(c, EM_EUNSUPPORTED,
                     "the factored pass needs D = 512 with Q a power-of-two multiple of 8 and a "
                     "matrix-core precision, or D = 2048 in fp16 / bf16 with Q a power-of-two "
-                    "multiple of 32");
+                    "multiple of 16");
     }
     const bool one_plane = c->prec == P_F16 || c->prec == P_BF16;
     if (one_plane && (c->flags & EM_FLAG_WIDE_PASS)) {

@@ -1815,22 +1815,26 @@ __global__ __launch_bounds__(kThreads) void pass_wide_kernel(PassArgs A) {
 //   Re <v_j, R_{o_i} a> = Re sum_k c_jk exp(-i k theta_i),   c_jk = sum_q conj(v_jkq) a_kq.
 // Per row this costs 4D + 4KW flops instead of 4DW, no template exists, and the pass is a stream
 // over the rows.  Each wave owns fac_rpw rows of a tile of 8 fac_rpw rows and holds them in
-// registers (lane l: entries EPL l .. EPL l + EPL - 1, so D = 64 EPL: EPL = 8 for D = 512, 32
-// for D = 2048 in one 16-bit plane; Q/EPL lanes share an angular frequency), while the next
-// tile's rows load.  c goes to LDS; C = [Re c | Im c] . [cos; sin] and
+// registers (lane l: entries EPL l .. EPL l + EPL - 1, so D = 64 EPL with EPL = 8 for D = 512;
+// Q/EPL lanes share an angular frequency), while the next tile's rows load.  For D = 2048 in one
+// 16-bit plane (EPL = 16) a row is split over a pair of waves: wave w holds half h = w % 2 of the
+// rows of its row group w / 2 (virtual lane 64 h + lane: entries 16 (64 h + lane) ..).  c goes to LDS; C = [Re c | Im c] . [cos; sin] and
 // U = w [Re E | Im E] are FP32 matrix-core products against the phase table (fragments in
 // registers when Wp <= 64, streamed from L2 otherwise); the posteriors as in the other passes;
 // the M-step from the rows in registers, the eight waves' partial sums added in wave order into
-// per-entry FP64 accumulators (EPL = 8: the waves' FP32 partials summed by entry owners; EPL = 32:
-// the waves add theirs in wave order into an FP64 copy of S in LDS).
+// per-entry FP64 accumulators (EPL = 8: the waves' FP32 partials summed by entry owners; EPL = 16:
+// the row groups add theirs in order into an FP64 copy of S in LDS).
 
-// rows per wave per tile: 2 for the 16-word row formats (FP32, bf16x3) and for 32 entries per
-// lane, 4 for one 16-bit plane at 8 entries per lane
+// rows per wave per tile: 2 for the 16-word row formats (FP32, bf16x3), 4 for one 16-bit plane
 __host__ __device__ constexpr int fac_rpw(int prec, int epl = 8) {
-    return (epl == 32 || prec == P_F32 || prec == P_BF16X3) ? 2 : 4;
+    return (epl == 8 && (prec == P_F32 || prec == P_BF16X3)) ? 2 : 4;
+}
+// rows per tile: 8 waves (EPL = 8) or 4 pairs of waves (EPL = 16) times the rows per wave
+__host__ __device__ constexpr int fac_bm(int prec, int epl = 8) {
+    return (epl == 16 ? 4 : 8) * fac_rpw(prec, epl);
 }
 constexpr int kFacFlush = 4;                  // tiles summed in FP32 before the FP64 flush
-constexpr int kFacFlush32 = 8;                // ... with 32 entries per lane
+constexpr int kFacFlush16 = 8;                // ... with 16 entries per lane
 
 constexpr int kFacPhLds = 2048;               // grid phase table staged in LDS up to this L
 
@@ -1846,7 +1850,7 @@ __host__ __device__ inline FacLds fac_lds(int K, int D, int Wp, int KCM, int BM,
     l.off_cs = align_up(BM * l.CBW * 4, 16);
     l.off_u = align_up(l.off_cs + BM * l.CSW * 4, 16);
     l.off_sw = align_up(l.off_u + BM * K * 8, 16);
-    l.off_f = align_up(l.off_sw + (EPL == 32 ? D * 16 : 8 * (9 * D / 8) * 8), 16);
+    l.off_f = align_up(l.off_sw + (EPL == 16 ? D * 16 : 8 * (9 * D / 8) * 8), 16);
     l.off_lr = l.off_f + 2 * BM * 4;
     l.off_a = align_up(l.off_lr + Wp * 4, 16);
     l.off_ph = align_up(l.off_a + D * 8, 16);
@@ -1908,6 +1912,7 @@ __device__ __forceinline__ void u_mfma_ph(const float *Cs, int CSW, const float2
         const bool im = col >= K;
         int mi = cok ? (int)(((int64_t)kq * ((lo + g) % L)) % L) : 0;
         const int step = cok ? (4 * kq) % L : 0;
+#pragma unroll 4
         for (int kk = 0; kk < KG; ++kk) {
             const int i = 4 * kk + g;
             float b = 0.f;
@@ -1987,9 +1992,11 @@ struct FacRow {
 template <int P, int WIDE, int KCM, int EPL>
 __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
     static_assert(P != P_F64, "matrix-core precisions");
-    static_assert(EPL == 8 || (EPL == 32 && WIDE && (P == P_F16 || P == P_BF16)),
-                  "32 entries per lane: one 16-bit plane, phase fragments from L2");
-    constexpr int RPW = fac_rpw(P, EPL), BM = 8 * RPW, DPT = 64 * EPL / kThreads;
+    static_assert(EPL == 8 || (EPL == 16 && WIDE && (P == P_F16 || P == P_BF16)),
+                  "16 entries per lane: one 16-bit plane, phase factors not in registers");
+    constexpr bool HR = EPL == 16;                 // a row over a pair of waves
+    constexpr int NVL = HR ? 128 : 64;             // virtual lanes of a row: D = NVL EPL
+    constexpr int RPW = fac_rpw(P, EPL), BM = fac_bm(P, EPL), DPT = NVL * EPL / kThreads;
     if ((A.flags & PF_CHECK_STOP) && *A.stopped) return;
 
     extern __shared__ __align__(16) uint8_t smem[];
@@ -1997,6 +2004,8 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int g = lane >> 4, c = lane & 15;
     const int K = A.K, D = A.D, Wp = A.Wp, NT = Wp / 16;
+    const int hh = HR ? (wave & 1) : 0, rg = HR ? (wave >> 1) : wave;   // half, row group
+    const int vl = 64 * hh + lane;                 // this lane's place in the row
     // long windows on the grid: the phase factors come from an LDS copy of the grid phase table
     const bool use_ph = WIDE && A.grid && A.L <= kFacPhLds;
     const FacLds LY = fac_lds(K, D, Wp, KCM, BM, EPL, use_ph ? A.L : 0);
@@ -2016,12 +2025,12 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
     float2 *as = (float2 *)(smem + LY.off_a);
     for (int i = tid; i < Wp; i += kThreads) lrs[i] = A.logrho32[i];
     for (int d = tid; d < D; d += kThreads)
-        as[(d % EPL) * 64 + d / EPL] = make_float2((float)A.a[2 * d], (float)A.a[2 * d + 1]);
-    if constexpr (EPL == 32)
+        as[(d % EPL) * NVL + d / EPL] = make_float2((float)A.a[2 * d], (float)A.a[2 * d + 1]);
+    if constexpr (HR)
         for (int d = tid; d < D; d += kThreads) ((double2 *)Sw)[d] = make_double2(0.0, 0.0);
 
     // this lane's entries and their coefficients a (FP32), its angular frequency and lane group
-    const int d0 = EPL * lane;
+    const int d0 = EPL * vl;
     const int LPK = A.Q / EPL;
     const int kl = d0 / A.Q;
     __syncthreads();
@@ -2053,11 +2062,12 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
     FacRow<P, EPL> vn[RPW];
     float rsn[RPW];
     auto load_tile = [&](int64_t t) {
-        const int64_t rb = A.row_begin + t * BM + RPW * wave;
+        const int64_t rb = A.row_begin + t * BM + RPW * rg;
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
             const int64_t row = rb + r < A.row_end ? rb + r : A.row_end - 1;
-            vn[r].load(A.V + row * A.rowbytes, A.Dp, lane);
+            // (the second half of a split row starts after D/2 entries of 4 bytes)
+            vn[r].load(A.V + row * A.rowbytes + (HR ? hh * (D / 2) * 4 : 0), A.Dp, lane);
             rsn[r] = A.rowscale ? A.rowscale[row] : 1.0f;
         }
     };
@@ -2066,17 +2076,18 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
     for (int e = 0; e < EPL; ++e) sr[e] = si[e] = 0.f;
     int nacc = 0;
     auto flush = [&]() {
-      if constexpr (EPL == 32) {
-        // the eight waves add their FP32 partials into the FP64 copy of S in wave order
+      if constexpr (HR) {
+        // the four row groups add their FP32 partials into the FP64 copy of S in order (the two
+        // halves of a group own disjoint entries)
         double2 *Sd = (double2 *)Sw;
-        for (int w = 0; w < 8; ++w) {
-            if (wave == w)
+        for (int w = 0; w < 4; ++w) {
+            if (rg == w)
 #pragma unroll
                 for (int e = 0; e < EPL; ++e) {
-                    double2 t = Sd[EPL * lane + e];
+                    double2 t = Sd[d0 + e];
                     t.x += (double)sr[e];
                     t.y += (double)si[e];
-                    Sd[EPL * lane + e] = t;
+                    Sd[d0 + e] = t;
                 }
             lds_barrier();
         }
@@ -2109,9 +2120,9 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
         nacc = 0;
     };
     int64_t tile = blockIdx.x;
-    // EPL = 8: the next tile's rows load into registers while this one is used; EPL = 32 (rows of
-    // 32 words per lane) loads each tile at its start, the register file holding one tile
-    constexpr bool kPrefetch = EPL == 8;
+    // EPL = 8: the next tile's rows load into registers while this one is used; EPL = 16 loads
+    // each tile at its start (the register file holds one tile of its rows)
+    constexpr bool kPrefetch = !HR;
     if (kPrefetch && tile < ntiles) load_tile(tile);
     for (; tile < ntiles; tile += gridDim.x) {
         const int64_t r0 = A.row_begin + tile * BM;
@@ -2129,14 +2140,12 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
         // ---- c_jk for this wave's rows; row factors
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
-            const int j = RPW * wave + r;
+            const int j = RPW * rg + r;
             float cr = 0.f, ci = 0.f;
 #pragma unroll
             for (int e = 0; e < EPL; ++e) {
-                // (32 entries per lane: the coefficient reads in groups of 8, not all at once)
-                if (EPL == 32 && e % 8 == 0) asm volatile("" ::: "memory");
                 const float2 v = vc[r].entry(e);
-                const float2 av = as[e * 64 + lane];
+                const float2 av = as[e * NVL + vl];
                 cr += v.x * av.x + v.y * av.y;            // Re conj(v) a
                 ci += v.x * av.y - v.y * av.x;            // Im conj(v) a
             }
@@ -2181,7 +2190,7 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
                 const int m = p % MT, n = p / MT;
                 f32x4 cacc = (f32x4){0.f, 0.f, 0.f, 0.f};
                 const float *eb = A.E2 + (int64_t)(16 * n + c) * 2 * K;
-#pragma unroll(EPL == 32 ? 8 : KCM)
+#pragma unroll 8
                 for (int kk = 0; kk < KCM; ++kk) {
                     const int colk = 4 * kk + g;
                     const float b = colk < 2 * K ? eb[colk] : 0.f;
@@ -2215,7 +2224,7 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
         // in FP32 over kFacFlush tiles, then the eight waves' partials in wave order into FP64
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
-            const int j = RPW * wave + r;
+            const int j = RPW * rg + r;
             const float2 u = j < rows ? Us[j * K + kl] : make_float2(0.f, 0.f);
 #pragma unroll
             for (int e = 0; e < EPL; ++e) {
@@ -2224,10 +2233,10 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
                 si[e] += u.x * v.y + u.y * v.x;
             }
         }
-        if (++nacc == (EPL == 32 ? kFacFlush32 : kFacFlush) || tile + gridDim.x >= ntiles) flush();
+        if (++nacc == (HR ? kFacFlush16 : kFacFlush) || tile + gridDim.x >= ntiles) flush();
     }
     __syncthreads();
-    if constexpr (EPL == 32) {
+    if constexpr (HR) {
 #pragma unroll
         for (int cc = 0; cc < DPT; ++cc) {
             const int d = tid + cc * kThreads;
@@ -2783,7 +2792,7 @@ const char *pass_wide_name(int prec, int NTW, int UR) {
     X(P_BF16X3, 0, 16, 8) X(P_BF16X3, 1, 16, 8) X(P_BF16X3, 0, 32, 8) X(P_BF16X3, 1, 32, 8)     \
     X(P_F16, 0, 16, 8) X(P_F16, 1, 16, 8) X(P_F16, 0, 32, 8) X(P_F16, 1, 32, 8)                 \
     X(P_BF16, 0, 16, 8) X(P_BF16, 1, 16, 8) X(P_BF16, 0, 32, 8) X(P_BF16, 1, 32, 8)             \
-    X(P_F16, 1, 16, 32) X(P_F16, 1, 32, 32) X(P_BF16, 1, 16, 32) X(P_BF16, 1, 32, 32)
+    X(P_F16, 1, 16, 16) X(P_F16, 1, 32, 16) X(P_BF16, 1, 16, 16) X(P_BF16, 1, 32, 16)
 
 static pass_fn find_fac(int prec, int WIDE, int KCM, int EPL) {
 #define SEM_X(P, Wd, KC, E)                                                                    \
@@ -2797,14 +2806,14 @@ bool fac_plan(int prec, int D, int Q, int K, int Wp, int gridL, size_t lds_max, 
               int *KCM, int *EPL, size_t *lds, int *BM) {
     int epl = 0;
     if (D == 512 && Q % 8 == 0) epl = 8;
-    else if (D == 2048 && (prec == P_F16 || prec == P_BF16) && Q % 32 == 0) epl = 32;
+    else if (D == 2048 && (prec == P_F16 || prec == P_BF16) && Q % 16 == 0) epl = 16;
     else return false;
     const int lpk = Q / epl;
     if (lpk & (lpk - 1)) return false;                       // lanes per frequency: 2^n
     const int kcm = 2 * K <= 64 ? 16 : (2 * K <= 128 ? 32 : 0);
-    const int wide = (epl == 32 || Wp > 64) ? 1 : 0;
+    const int wide = (epl == 16 || Wp > 64) ? 1 : 0;
     if (!kcm || !find_fac(prec, wide, kcm, epl)) return false;
-    const int bm = 8 * fac_rpw(prec, epl);
+    const int bm = fac_bm(prec, epl);
     const int phl = (wide && gridL > 0 && gridL <= kFacPhLds) ? gridL : 0;
     const size_t b = (size_t)fac_lds(K, D, Wp, kcm, bm, epl, phl).total;
     if (b > lds_max) return false;
@@ -2837,7 +2846,7 @@ hipError_t pass_fac_setup(int prec, int WIDE, int KCM, int EPL, size_t lds, int 
 const char *pass_fac_name(int prec, int WIDE, int KCM, int EPL) {
     static char buf[64];
     snprintf(buf, sizeof buf, "pass_fac_kernel<%s,BM=%d,%s,KC=%d%s>", kPrecName[prec],
-             8 * fac_rpw(prec, EPL), WIDE ? "L2" : "reg", KCM, EPL == 32 ? ",E32" : "");
+             fac_bm(prec, EPL), WIDE ? "L2" : "reg", KCM, EPL == 16 ? ",E16" : "");
     return buf;
 }
 

@@ -138,7 +138,7 @@ def test_factored_rejects_unsupported_shapes(gpu):
 
 
 SHAPES2048 = {
-    # name: (K, Q, L, half window, N): 32 entries per lane, D = 2048
+    # name: (K, Q, L, half window, N): 16 entries per lane (rows over wave pairs), D = 2048
     "c5": (64, 32, 720, 90, 3001),         # the large-image shape, W = 181
     "c5narrow": (64, 32, 720, 45, 1001),   # W = 91
     "q64": (32, 64, 360, 24, 777),         # two lanes per frequency, 2K = 64, W = 49
@@ -164,7 +164,7 @@ def test_factored_2048_teacher_forced_step(gpu, prec, shape):
     print(f"factored D=2048 shape={shape} prec={prec} N={N} W={W}", flush=True)
     em = EM(torch.from_numpy(V.astype(np.complex64)).to(gpu), K=K, Q=Q, L=L, sigma2=s2,
             window=(lo, W), prior=rb, gamma=50.0, precision=prec, factored=True)
-    assert em.info()["kernel"].startswith("pass_fac_kernel") and "E32" in em.info()["kernel"]
+    assert em.info()["kernel"].startswith("pass_fac_kernel") and "E16" in em.info()["kernel"]
     em.set_state(a_t, rho_t, 0)
     offs = oracle.offsets(lo, W)
     wg, am, mg = em.posterior()
@@ -205,7 +205,7 @@ def test_factored_2048_full_size(gpu):
     a_t = 0.9 * a_true + 0.05 * np.sqrt(s2) * (rng.standard_normal(w.D) + 1j * rng.standard_normal(w.D))
     em = EM(obs, K=w.K, Q=w.Q, L=w.L, sigma2=s2, window=(lo, W), prior=rb, gamma=w.gamma,
             precision="fp16", timing=True, factored=True)
-    assert "E32" in em.info()["kernel"], em.info()
+    assert "E16" in em.info()["kernel"], em.info()
     em.set_state(a_t, rb, 0)
     offs = oracle.offsets(lo, W)
     for (r0, n) in ((0, 512), (w.N - 512, 512)):
