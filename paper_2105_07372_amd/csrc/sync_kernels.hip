@@ -9,7 +9,8 @@
 //                   in FP64
 //   nearest_kernel  for each observation the nearest member of S_P (squared distance without
 //                   rotation, ||v_n||^2 - 2 Re <v_i, v_n>, on FP32 matrix cores), the member itself
-//                   excluded, with the gap to the runner-up
+//                   excluded, with the gap to the runner-up (nearest_lds_kernel: rows up to 1024
+//                   reals staged in LDS, 32 per workgroup)
 //   gather / align  theta_i = phi_{nn_i}; v_i o exp(+i kbar theta_i)
 //
 // Ties in an argmax or argmin go to the lowest index.
@@ -346,6 +347,86 @@ __global__ __launch_bounds__(kSyncThreads) void nearest_kernel(const float2 *V, 
     }
 }
 
+// The same search for 32 observations per workgroup of 512 threads, their rows staged once in
+// LDS (rows padded by 4 floats so that the 16 lanes of a row group read distinct banks): wave w
+// takes the reference tiles w, w + 8, ..; each 16-byte reference load serves the four MFMA
+// k-steps of both 16-row halves.  For 2D <= 1024 and 2D % 16 == 0.
+constexpr int kNnThreads = 512;
+__global__ __launch_bounds__(kNnThreads) void nearest_lds_kernel(const float2 *V, int64_t N,
+                                                                 int64_t P, int D,
+                                                                 const float *nrm, int *nn,
+                                                                 float *gap) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int RS = 2 * D + 4;                               // floats per staged row
+    float *Aq = (float *)smem;
+    Top2 *red = (Top2 *)(Aq + 32 * RS);                     // 8 waves x 32 rows
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int g = lane >> 4, c = lane & 15;
+    const int64_t r0 = (int64_t)blockIdx.x * 32;
+    const int F4 = 2 * D / 4;                               // float4 per row
+    for (int q = t; q < 32 * F4; q += kNnThreads) {
+        const int r = q / F4, f = q - r * F4;
+        const int64_t row = r0 + r < N ? r0 + r : N - 1;
+        *(float4 *)(Aq + r * RS + 4 * f) = ((const float4 *)(V + row * D))[f];
+    }
+    __syncthreads();
+    const int NC = 2 * D / 16;
+    Top2 best[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) best[q] = Top2{-INFINITY, 0x7fffffff, -INFINITY};
+    const int64_t NTr = (P + 15) / 16;
+    const float *a0p = Aq + c * RS + 4 * g, *a1p = Aq + (16 + c) * RS + 4 * g;
+    for (int64_t n = wave; n < NTr; n += kNnThreads / 64) {
+        const int64_t ref = 16 * n + c;
+        const float4 *rb = (const float4 *)(V + (ref < P ? ref : P - 1) * D);
+        f32x4s acc0 = (f32x4s){0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
+        for (int sc = 0; sc < NC; ++sc) {
+            const float4 b = rb[4 * sc + g];
+            const float4 a0 = *(const float4 *)(a0p + 16 * sc);
+            const float4 a1 = *(const float4 *)(a1p + 16 * sc);
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.x, b.x, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.x, b.x, acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.y, b.y, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.y, b.y, acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.z, b.z, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.z, b.z, acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.w, b.w, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.w, b.w, acc1, 0, 0, 0);
+        }
+        if (ref < P) {
+            const float nr = nrm[ref];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (r0 + 4 * g + q != ref)
+                    best[q] = top2_merge(best[q], Top2{2.f * acc0[q] - nr, (int)ref, -INFINITY});
+                if (r0 + 16 + 4 * g + q != ref)
+                    best[4 + q] =
+                        top2_merge(best[4 + q], Top2{2.f * acc1[q] - nr, (int)ref, -INFINITY});
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+        for (int m = 1; m < 16; m <<= 1) best[q] = top2_merge(best[q], top2_shfl_xor(best[q], m));
+    if (c == 0)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            red[wave * 32 + 4 * g + q] = best[q];
+            red[wave * 32 + 16 + 4 * g + q] = best[4 + q];
+        }
+    __syncthreads();
+    if (t < 32) {
+        Top2 r = red[t];
+        for (int w = 1; w < kNnThreads / 64; ++w) r = top2_merge(r, red[w * 32 + t]);
+        const int64_t row = r0 + t;
+        if (row < N) {
+            nn[row] = r.i;
+            gap[row] = r.b - r.s;
+        }
+    }
+}
+
 // (an index outside [0, P), left by non-finite distances, gives NaN instead of a read)
 __global__ void gather_kernel(const double *phi, int64_t P, const int *nn, int64_t N,
                               double *theta) {
@@ -458,6 +539,15 @@ hipError_t launch_nearest(const float2 *V, int64_t N, int64_t P, int D, float *n
                           float *gap, hipStream_t s) {
     hipLaunchKernelGGL(rownorm_kernel, dim3((unsigned)((P + 3) / 4)), dim3(256), 0, s, V, P, D,
                        nrm);
+    if (2 * D <= 1024 && (2 * D) % 16 == 0) {
+        const size_t lds = (size_t)32 * (2 * D + 4) * 4 + (size_t)8 * 32 * sizeof(Top2);
+        hipError_t e = hipFuncSetAttribute((const void *)nearest_lds_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) (void)hipGetLastError();
+        hipLaunchKernelGGL(nearest_lds_kernel, dim3((unsigned)((N + 31) / 32)), dim3(kNnThreads),
+                           lds, s, V, N, P, D, nrm, nn, gap);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(nearest_kernel, dim3((unsigned)((N + 15) / 16)), dim3(kSyncThreads), 0, s,
                        V, N, P, D, nrm, nn, gap);
     return hipGetLastError();

@@ -67,7 +67,8 @@ def test_ppm_matches_oracle(gpu):
         assert np.abs(np.angle(np.exp(1j * (th - to)))).max() <= 1e-9, iters
 
 
-@pytest.mark.parametrize("K,Q,N,P", [(8, 8, 3001, 200), (16, 8, 1000, 1000), (4, 2, 517, 37)])
+@pytest.mark.parametrize("K,Q,N,P", [(8, 8, 3001, 200), (16, 8, 1000, 1000), (4, 2, 517, 37),
+                                     (32, 32, 600, 100)])   # the last: rows too long for LDS
 def test_nearest_neighbours(gpu, K, Q, N, P):
     import torch
     from paper_2105_07372_amd import nearest
