@@ -167,7 +167,10 @@ em_status em_learn_prior(const int32_t *err_dev, int64_t n, int32_t L, int32_t l
 /* ---- Synchronize and Match: the step before the EM path (§II-A, §III-A).
  * These calls take the caller's observations directly (device, N x D complex64, row-major, the
  * same layout as em_init; not copied), run on stream and synchronise it, allocate their own
- * scratch and free it before returning.  Failures are reported through em_last_error(NULL).
+ * scratch and free it before returning.  They return EM_EINVAL for a missing pointer or a size
+ * out of range (before any device work), EM_EUNSUPPORTED beyond the stated limits, EM_ENOMEM
+ * when scratch cannot be allocated, EM_EDEVICE for a failed HIP call; em_last_error(NULL)
+ * describes the failure.
  * Observations must be finite (not checked here; em_init checks them).  Ties in an argmax or
  * argmin go to the lowest index.  Sign conventions: R_l v = v o exp(-i kbar 2 pi l / L); rel[i][j]
  * is the grid rotation that best maps v_j onto v_i, an estimate of theta_i - theta_j; the
@@ -201,8 +204,8 @@ em_status em_sync_match(const void *obs_dev, int64_t N, int32_t K, int32_t Q, in
                         int64_t P, int32_t iters, double *theta_dev, int32_t *nn_dev,
                         void *stream);
 
-/* Aligned observations (§II-A): out[i] = v_i o exp(+i kbar theta_i), complex64, N x D (may not
- * alias obs_dev). */
+/* Aligned observations (§II-A): out[i] = v_i o exp(+i kbar theta_i), complex64, N x D (device,
+ * caller-owned, must not overlap obs_dev). */
 em_status em_align(const void *obs_dev, int64_t N, int32_t K, int32_t Q, const double *theta_dev,
                    void *out_dev, void *stream);
 
@@ -216,7 +219,9 @@ em_status em_aligned_mean(const void *obs_dev, int64_t N, int32_t K, int32_t Q,
 /* Binned centred errors of a synchronizer (§III-B, Algorithm "learning rotation distribution"):
  * bins_dev[i] = floor((theta_hat_i - theta_i - 2 pi lc / L) L / (2 pi)) mod L (FP64), for
  * em_learn_prior.  theta_hat_dev, theta_dev: N doubles (radians); lc: the centring rotation on
- * the grid (em_relative_rotations of the true image and the aligned mean gives it). */
+ * the grid (em_relative_rotations of the true image and the aligned mean gives it).  After
+ * alignment the windowed EM's rotation variable is the negated error: its prior is the histogram
+ * of the bins computed with the two angle arrays swapped and -lc. */
 em_status em_error_bins(const double *theta_hat_dev, const double *theta_dev, int64_t N, int32_t L,
                         int32_t lc, int32_t *bins_dev, void *stream);
 
