@@ -2,13 +2,16 @@
 
 Default workload: windowed Synch-EM on N=100000 observations of D=512 steerable coefficients
 (K=32 angular x Q=16 radial), L=360 rotations, a window of W=49 offsets (+-3 sigma of an 8 degree
-post-synchronisation error), learned histogram prior with gamma=100, bf16 split-precision
-correlations (observations and template each bf16 hi+lo, three products, FP32 accumulation).
-One step is one EM iteration over all N observations (E-step correlations, prior-weighted
-posterior, fused M-step accumulation, FP64 finalize, next template).  The same run times the
-plain full-search FP32 EM (all 360 rotations, uniform prior) on the same observations, the fp16
-windowed variant, the factored E-step (per-frequency sums, an exact rewrite of the correlation:
-windowed FP32 / fp16 and full search FP32), and the FP64 CPU oracle on the host cores.
+post-synchronisation error), learned histogram prior with gamma=100.  One step is one EM
+iteration over all N observations (E-step correlations, prior-weighted posterior, fused M-step
+accumulation, FP64 finalize).  The headline runs the factored E-step in FP32: the correlations
+through the per-frequency sums c_jk = sum_q conj(v_jkq) a_kq, an exact rewrite of the contraction
+against the W rotated templates, with FP32 arithmetic on FP32 observations.  The same run times
+the contraction itself as a correlation GEMM (bf16 split precision: observations and template
+each bf16 hi+lo, three products, FP32 accumulation; and fp16), the factored E-step on bf16 hi+lo
+and fp16 observations, the refined-resolution window, the plain full-search FP32 EM (all 360
+rotations, uniform prior; correlation GEMM and factored), Synchronize and Match, and the FP64 CPU
+oracle on the host cores.
 
 Prints one JSON line.  --gpus N with N > 1 is refused: the path runs on one GPU.
 """
@@ -102,7 +105,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--precision", default="bf16x3")
+    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--correlation", action="store_true",
+                    help="run the headline with the correlation GEMM against the rotated "
+                         "templates instead of the factored E-step")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-baseline", action="store_true", help="skip the full-search FP32 run")
     ap.add_argument("--no-sync", action="store_true", help="skip the Synchronize-and-Match timing")
@@ -111,6 +117,8 @@ def main():
                     help="only run a plain device-to-device copy of MIB MiB (calibrates the HBM "
                          "byte counters of a profiler run) and exit")
     args = ap.parse_args()
+    if args.precision == "fp64":
+        args.correlation = True          # the factored pass runs on the matrix-core precisions
     if args.gpus != 1:
         print(f"bench.py: the path runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU form would split the observations and all-reduce the FP64 "
@@ -146,7 +154,7 @@ def main():
 
     # --- headline: windowed, learned prior, gamma = 100
     em = EM(obs, K=w.K, Q=w.Q, L=w.L, sigma2=s2, window=(lo, W), prior=rb, gamma=w.gamma,
-            precision=args.precision, timing=True)
+            precision=args.precision, timing=True, factored=not args.correlation)
     info = em.info()
     log(f"bench: windowed {args.precision} {info}")
     dt, pass_ms, nlaunch = time_em(em, args.steps, args.warmup, (a0, rb, 0))
@@ -161,16 +169,18 @@ def main():
     log(f"bench: windowed {iters_s:.1f} it/s, pass {pass_ms * 1e3:.1f} us")
 
     variants = {}
-    runs = [(f"windowed_{p}", dict(precision=p)) for p in ("fp16",) if args.precision != "fp16"]
-    # the factored E-step (per-frequency sums, an exact rewrite of the correlation)
-    runs += [(f"windowed_factored_{p}", dict(precision=p, factored=True)) for p in ("fp32", "fp16")]
+    # the correlation GEMM against the W rotated templates (the contraction as stated), and the
+    # factored E-step (per-frequency sums, an exact rewrite of it) in the other precisions
+    runs = [(f"windowed_correlation_{p}", dict(precision=p)) for p in ("bf16x3", "fp16")
+            if not (args.correlation and p == args.precision)]
+    runs += [(f"windowed_factored_{p}", dict(precision=p, factored=True))
+             for p in ("fp32", "bf16x3", "fp16") if args.correlation or p != args.precision]
     # the refined-resolution window (Section III-C): as many angles as the window, sampled at
     # half-degree steps over the central +-12 degrees, prior shaped like the rotation law there
     ang = (np.arange(W) - W // 2) * np.pi / w.L
     rb_ang = np.exp(-0.5 * (np.degrees(ang) / w.rot_std_deg) ** 2)
     rb_ang /= rb_ang.sum()
-    runs += [(f"windowed_refined_{args.precision}",
-              dict(precision=args.precision, angles=ang, prior=rb_ang))]
+    runs += [("windowed_refined_bf16x3", dict(precision="bf16x3", angles=ang, prior=rb_ang))]
     for name, kw in runs:
         kw = dict(kw)
         pr = kw.pop("prior", rb)
@@ -265,12 +275,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"bf16x3": "bf16", "fp16": "fp16", "fp32": "fp32", "fp64": "fp64",
-                  "bf16": "bf16"}[args.precision],
+        # the arithmetic: the factored E-step computes in FP32 whatever the observations' storage
+        "dtype": ({"bf16x3": "bf16", "fp16": "fp16", "fp32": "fp32", "fp64": "fp64",
+                   "bf16": "bf16"}[args.precision] if args.correlation else "fp32"),
         "data": "synthetic",
         "config": {"workload": f"windowed Synch-EM N={w.N} D={w.D} (K={w.K},Q={w.Q}) L={w.L} "
-                               f"W={W} gamma={w.gamma} learned prior, {args.precision}",
-                   "N": w.N, "D": w.D, "L": w.L, "W": W, "precision": args.precision},
+                               f"W={W} gamma={w.gamma} learned prior, {args.precision}"
+                               + (", correlation GEMM" if args.correlation else ", factored E-step"),
+                   "N": w.N, "D": w.D, "L": w.L, "W": W, "precision": args.precision,
+                   "e_step": "correlation GEMM" if args.correlation else "factored"},
         "obs_rot_per_s": iters_s * w.N * W,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,

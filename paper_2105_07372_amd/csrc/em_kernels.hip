@@ -672,6 +672,22 @@ __device__ __forceinline__ float row16_sum(float v) {
     v += dpp_f<0x141>(v);
     return v + dpp_f<0x140>(v);
 }
+// Sum over aligned groups of a power-of-two number of consecutive lanes by DPP without branches:
+// xor 1 and xor 2 inside quads, then the half-row and row mirrors (each step adds two groups that
+// are already uniform); step t counts with weight f[t] = 1 while the group is wider than 2^t
+// lanes, else 0 (x * 0 + v = v exactly for finite x), so groups up to 16 lanes end here and wider
+// ones continue with xor 16, 32.  Every lane ends with its group's sum; every lane must be active.
+__device__ __forceinline__ float lanes_sum_dpp(float v, const float (&f)[4]) {
+    v = fmaf(dpp_f<0xB1>(v), f[0], v);
+    v = fmaf(dpp_f<0x4E>(v), f[1], v);
+    v = fmaf(dpp_f<0x141>(v), f[2], v);
+    return fmaf(dpp_f<0x140>(v), f[3], v);
+}
+// Exchange with lane ^ 16 inside each 32-lane half (ds_swizzle, bit mode: and 0x1f, xor 0x10).
+__device__ __forceinline__ float swz_xor16(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v),
+                                                                 0x401F));
+}
 // Reductions over groups of `width` consecutive lanes: 16-lane rows by DPP, wider groups add
 // cross-row shuffles.
 template <typename T>
@@ -679,7 +695,8 @@ __device__ __forceinline__ T rows_max(T v, int width) {
     if constexpr (sizeof(T) == 4) {
         if (width >= 16) {
             v = row16_max(v);
-            for (int o = 16; o < width; o <<= 1) v = fmaxf(v, __shfl_xor(v, o));
+            if (width >= 32) v = fmaxf(v, swz_xor16(v));
+            if (width >= 64) v = fmaxf(v, __shfl_xor(v, 32));
             return v;
         }
     }
@@ -690,7 +707,8 @@ __device__ __forceinline__ T rows_sum(T v, int width) {
     if constexpr (sizeof(T) == 4) {
         if (width >= 16) {
             v = row16_sum(v);
-            for (int o = 16; o < width; o <<= 1) v += __shfl_xor(v, o);
+            if (width >= 32) v += swz_xor16(v);
+            if (width >= 64) v += __shfl_xor(v, 32);
             return v;
         }
     }
@@ -784,6 +802,51 @@ __device__ __forceinline__ void tile_rows(const PassArgs &A, int CSW, typename P
             acc.rows += 1.0;
             if (A.flags & PF_STORE_LSE) A.lse[r0 + r] = (double)lse;
         }
+    }
+}
+
+// tile_rows for windows of at most 64 offsets and no posterior queries: each of the TPR threads
+// of a row keeps its 64 / TPR log-weights in registers and takes one exponential per entry
+// (w = exp(l - m) / s with s = sum exp(l - m)).  Columns W .. 63 get zero posteriors.
+template <int BM, int DPT>
+__device__ __forceinline__ void tile_rows_short(const PassArgs &A, int CSW, float *Cs,
+                                                const float *lr32, int64_t r0, int rows,
+                                                PassAcc<DPT> &acc) {
+    constexpr int TPR = kThreads / BM, NC = 64 / TPR;
+    static_assert(NC * TPR == 64, "a row's threads cover 64 columns");
+    const int tid = threadIdx.x, r = tid / TPR, sub = tid % TPR;
+    const bool valid = r < rows;
+    float *crow = Cs + r * CSW;
+    float l[NC], e[NC];
+    float m = -INFINITY;
+#pragma unroll
+    for (int t = 0; t < NC; ++t) {
+        l[t] = crow[sub + TPR * t];
+        if (sub + TPR * t < A.W) m = fmaxf(m, l[t]);
+    }
+    m = rows_max(m, TPR);
+    float s = 0.f;
+#pragma unroll
+    for (int t = 0; t < NC; ++t) {
+        e[t] = sub + TPR * t < A.W ? __expf(l[t] - m) : 0.f;
+        s += e[t];
+    }
+    s = rows_sum(s, TPR);
+    const float lse = m + __logf(s), inv = 1.0f / s;
+    float wc = 0.f;
+#pragma unroll
+    for (int t = 0; t < NC; ++t) {
+        const int i = sub + TPR * t;
+        const float w = valid ? e[t] * inv : 0.f;
+        if (w > 0.f) wc += w * (l[t] - lr32[i]);
+        crow[i] = w;
+    }
+    wc = rows_sum(wc, TPR);
+    if (sub == 0 && valid) {
+        acc.lse += (double)lse;
+        acc.wc += (double)wc;                     // sum_i w_ji (l_ji - log rho_i)
+        acc.rows += 1.0;
+        if (A.flags & PF_STORE_LSE) A.lse[r0 + r] = (double)lse;
     }
 }
 
@@ -1528,7 +1591,7 @@ __device__ __forceinline__ void u_wide_reg(const float *Cs, int CSW, const float
                                            int K, const float *rowu, float2 *Us, int ucol) {
     constexpr int MS = UR / 16;
     const int lane = threadIdx.x & 63, g = lane >> 4, rl = lane & 15;
-    if ((threadIdx.x >> 6) * 16 >= 2 * K) return;
+    if ((ucol & ~15) >= 2 * K) return;             // this wave's U column tile is past 2K
     f32x4 acc[MS];
 #pragma unroll
     for (int m = 0; m < MS; ++m) acc[m] = (f32x4){0.f, 0.f, 0.f, 0.f};
@@ -1944,6 +2007,48 @@ __device__ __forceinline__ void u_mfma_ph(const float *Cs, int CSW, const float2
     }
 }
 
+// U (BM x 2K) = w (BM x 64) . [Re E | Im E] for windows of at most 64 offsets, this wave's B
+// fragments in registers.  The sum over the window runs in a permuted order: lane (g, rl) takes
+// window index 16 g + kk at k-step kk (ereg[kk] = E2[16 g + kk][ucol]), so its A values are 16
+// consecutive posteriors of row rl, read as four 16-byte words.
+template <int BM>
+__device__ __forceinline__ void u_fac_reg(const float *Cs, int CSW, const float (&ereg)[16],
+                                          int K, const float *rowu, float2 *Us, int ucol) {
+    constexpr int MS = BM / 16;
+    const int lane = threadIdx.x & 63, g = lane >> 4, rl = lane & 15;
+    if ((ucol & ~15) >= 2 * K) return;             // this wave's U column tile is past 2K
+    f32x4 acc[MS];
+#pragma unroll
+    for (int m = 0; m < MS; ++m) acc[m] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int m = 0; m < MS; ++m) {
+        const float4 *ar = (const float4 *)(Cs + (m * 16 + rl) * CSW + 16 * g);
+        float4 a4[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) a4[t] = ar[t];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[t].x, ereg[4 * t], acc[m], 0, 0, 0);
+            acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[t].y, ereg[4 * t + 1], acc[m], 0, 0, 0);
+            acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[t].z, ereg[4 * t + 2], acc[m], 0, 0, 0);
+            acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[t].w, ereg[4 * t + 3], acc[m], 0, 0, 0);
+        }
+    }
+    if (ucol < 2 * K) {
+#pragma unroll
+        for (int m = 0; m < MS; ++m)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = m * 16 + 4 * g + q;
+                const float v = acc[m][q] * rowu[row];
+                if (ucol < K)
+                    Us[row * K + ucol].x = v;
+                else
+                    Us[row * K + ucol - K].y = v;
+            }
+    }
+}
+
 // Words of one stored row for lane l (entries EPL l .. EPL l + EPL - 1): FP32 2 EPL words
 // (re, im per entry); bf16x3 EPL hi words then EPL lo words; fp16 / bf16 EPL words.
 template <int P, int EPL = 8>
@@ -2033,25 +2138,37 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
     const int d0 = EPL * vl;
     const int LPK = A.Q / EPL;
     const int kl = d0 / A.Q;
+    float lpk_f[4];                                // the DPP steps of the LPK-lane sums
+#pragma unroll
+    for (int t = 0; t < 4; ++t) lpk_f[t] = LPK > (1 << t) ? 1.f : 0.f;
+    // columns 2K .. 4 KCM - 1 of the c rows stay zero for the whole pass
+    for (int x = tid; x < BM * (4 * KCM - 2 * K); x += kThreads) {
+        const int j = x / (4 * KCM - 2 * K);
+        cb[j * LY.CBW + 2 * K + x % (4 * KCM - 2 * K)] = 0.f;
+    }
     __syncthreads();
-    // C product: wave w computes rows 16 (w >> 2) .. of window tile (w & 3) (Wp <= 64); its B
-    // fragments E2[16 n + c][4 kk + g] (zero past 2K)
+    // C product: wave w computes rows 16 (w >> 2) .. of window tile (w & 3) (Wp <= 64); the sum
+    // over [Re c | Im c] runs in a permuted order (lane group g takes columns KCM g .. KCM g +
+    // KCM - 1, read as 16-byte words), so its B fragments are E2[16 n + c][KCM g + kk] (zero past
+    // 2K)
     float cfr[KCM];
     const int cm = wave >> 2, cn = wave & 3;       // (16-row tiles: waves 0-3 only)
     if constexpr (!WIDE) {
 #pragma unroll
         for (int kk = 0; kk < KCM; ++kk) {
-            const int col = 4 * kk + g, i = 16 * cn + c;
+            const int col = KCM * g + kk, i = 16 * cn + c;
             cfr[kk] = (col < 2 * K && i < Wp) ? A.E2[(int64_t)i * 2 * K + col] : 0.f;
         }
     }
-    // U product: wave w computes U columns 16 w + c over 16 k-steps (Wp <= 64)
-    const int ucol = wave * 16 + c;
+    // U product: wave w computes U columns 16 (w ^ 4) + c over 16 k-steps (Wp <= 64): for
+    // 2K <= 64 the upper four waves, while wave 0 takes the W column sums; window index
+    // 16 g + kk at k-step kk (u_fac_reg)
+    const int ucol = (wave ^ 4) * 16 + c;
     float ereg[16];
     if constexpr (!WIDE) {
 #pragma unroll
         for (int kk = 0; kk < 16; ++kk) {
-            const int i = 4 * kk + g;
+            const int i = 16 * g + kk;
             ereg[kk] = (i < Wp && ucol < 2 * K) ? A.E2[(int64_t)i * 2 * K + ucol] : 0.f;
         }
     }
@@ -2137,7 +2254,13 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
         }
         if (kPrefetch && tile + gridDim.x < ntiles) load_tile(tile + gridDim.x);
 
-        // ---- c_jk for this wave's rows; row factors
+        // ---- c_jk for this wave's rows; row factors.  EPL = 8: the lane's coefficients are read
+        // from LDS once per tile, ahead of the rows
+        float2 areg[HR ? 1 : EPL];
+        if constexpr (!HR) {
+#pragma unroll
+            for (int e = 0; e < EPL; ++e) areg[e] = as[e * NVL + vl];
+        }
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
             const int j = RPW * rg + r;
@@ -2145,11 +2268,16 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
 #pragma unroll
             for (int e = 0; e < EPL; ++e) {
                 const float2 v = vc[r].entry(e);
-                const float2 av = as[e * NVL + vl];
-                cr += v.x * av.x + v.y * av.y;            // Re conj(v) a
-                ci += v.x * av.y - v.y * av.x;            // Im conj(v) a
+                float2 av;
+                if constexpr (HR) av = as[e * NVL + vl]; else av = areg[e];
+                cr = fmaf(v.x, av.x, cr);                 // Re conj(v) a
+                cr = fmaf(v.y, av.y, cr);
+                ci = fmaf(v.x, av.y, ci);                 // Im conj(v) a
+                ci = fmaf(-v.y, av.x, ci);
             }
-            for (int o = 1; o < LPK; o <<= 1) {
+            cr = lanes_sum_dpp(cr, lpk_f);
+            ci = lanes_sum_dpp(ci, lpk_f);
+            for (int o = 16; o < LPK; o <<= 1) {
                 cr += __shfl_xor(cr, o);
                 ci += __shfl_xor(ci, o);
             }
@@ -2157,7 +2285,6 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
                 cb[j * LY.CBW + kl] = cr;
                 cb[j * LY.CBW + K + kl] = ci;
             }
-            for (int col = 2 * K + lane; col < 4 * KCM; col += 64) cb[j * LY.CBW + col] = 0.f;
             if (lane == 0) {
                 const float u = j < rows ? rsc[r] : 1.0f;
                 rowf[j] = (float)A.coef * u;
@@ -2170,10 +2297,16 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
         if constexpr (!WIDE) {
           if (16 * cm < BM) {
             f32x4 cacc = (f32x4){0.f, 0.f, 0.f, 0.f};
+            const float4 *arow = (const float4 *)(cb + (16 * cm + c) * LY.CBW + KCM * g);
+            float4 a4[KCM / 4];
 #pragma unroll
-            for (int kk = 0; kk < KCM; ++kk) {
-                const float a = cb[(16 * cm + c) * LY.CBW + 4 * kk + g];
-                cacc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, cfr[kk], cacc, 0, 0, 0);
+            for (int t = 0; t < KCM / 4; ++t) a4[t] = arow[t];
+#pragma unroll
+            for (int t = 0; t < KCM / 4; ++t) {
+                cacc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[t].x, cfr[4 * t], cacc, 0, 0, 0);
+                cacc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[t].y, cfr[4 * t + 1], cacc, 0, 0, 0);
+                cacc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[t].z, cfr[4 * t + 2], cacc, 0, 0, 0);
+                cacc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[t].w, cfr[4 * t + 3], cacc, 0, 0, 0);
             }
             const int col = 16 * cn + c;
 #pragma unroll
@@ -2208,12 +2341,15 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
         lds_barrier();
 
         // ---- a4 + a5
-        tile_rows<P, BM, DPT>(A, LY.CSW, Cs, lrs, r0, rows, acc);
+        if (!WIDE && !(A.flags & (PF_QUERY | PF_LOAD_LSE)))
+            tile_rows_short<BM, DPT>(A, LY.CSW, Cs, lrs, r0, rows, acc);
+        else
+            tile_rows<P, BM, DPT>(A, LY.CSW, Cs, lrs, r0, rows, acc);
         if (!(A.flags & PF_ACC_M)) continue;
         lds_barrier();
         tile_wsum<P, DPT>(A, LY.CSW, Cs, rows, acc);
         if constexpr (!WIDE)
-            u_wide_reg<BM, 16>(Cs, LY.CSW, ereg, K, rowu, Us, ucol);
+            u_fac_reg<BM>(Cs, LY.CSW, ereg, K, rowu, Us, ucol);
         else
             if (use_ph)
                 u_mfma_ph<BM>(Cs, LY.CSW, phs, A.L, A.lo, A.W, Wp, K, rowu, Us);
@@ -2229,8 +2365,10 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
 #pragma unroll
             for (int e = 0; e < EPL; ++e) {
                 const float2 v = vc[r].entry(e);
-                sr[e] += u.x * v.x - u.y * v.y;
-                si[e] += u.x * v.y + u.y * v.x;
+                sr[e] = fmaf(u.x, v.x, sr[e]);            // Re (U v)
+                sr[e] = fmaf(-u.y, v.y, sr[e]);
+                si[e] = fmaf(u.x, v.y, si[e]);            // Im (U v)
+                si[e] = fmaf(u.y, v.x, si[e]);
             }
         }
         if (++nacc == (HR ? kFacFlush16 : kFacFlush) || tile + gridDim.x >= ntiles) flush();
