@@ -2252,7 +2252,10 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
             vc[r] = vn[r];
             rsc[r] = rsn[r];
         }
-        if (kPrefetch && tile + gridDim.x < ntiles) load_tile(tile + gridDim.x);
+        // the next tile's rows: waves 0-3 issue their loads now, waves 4-7 after the c barrier
+        // (issued all at once, the later waves' loads queue behind the earlier ones')
+        const bool pf = kPrefetch && tile + gridDim.x < ntiles;
+        if (pf && wave < 4) load_tile(tile + gridDim.x);
 
         // ---- c_jk for this wave's rows; row factors.  EPL = 8: the lane's coefficients are read
         // from LDS once per tile, ahead of the rows
@@ -2292,6 +2295,7 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
             }
         }
         lds_barrier();
+        if (pf && wave >= 4) load_tile(tile + gridDim.x);
 
         // ---- C = [Re c | Im c] . E2^T on FP32 matrix cores -> l' = coef C / s_j + log rho
         if constexpr (!WIDE) {
