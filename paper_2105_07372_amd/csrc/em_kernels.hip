@@ -805,44 +805,46 @@ __device__ __forceinline__ void tile_rows(const PassArgs &A, int CSW, typename P
     }
 }
 
-// tile_rows for windows of at most 64 offsets and no posterior queries: each of the TPR threads
-// of a row keeps its 64 / TPR log-weights in registers and takes one exponential per entry
-// (w = exp(l - m) / s with s = sum exp(l - m)).  Columns W .. 63 get zero posteriors.
+// tile_rows for windows of at most 64 offsets and no posterior queries: 16 threads per row (the
+// first 16 BM threads), each with 4 consecutive log-weights in registers (one 16-byte LDS read
+// and write), one exponential per entry (w = exp(l - m) / s with s = sum exp(l - m)) and DPP
+// row reductions.  Columns W .. 63 get zero posteriors.
 template <int BM, int DPT>
 __device__ __forceinline__ void tile_rows_short(const PassArgs &A, int CSW, float *Cs,
                                                 const float *lr32, int64_t r0, int rows,
                                                 PassAcc<DPT> &acc) {
-    constexpr int TPR = kThreads / BM, NC = 64 / TPR;
-    static_assert(NC * TPR == 64, "a row's threads cover 64 columns");
-    const int tid = threadIdx.x, r = tid / TPR, sub = tid % TPR;
+    static_assert(16 * BM <= kThreads, "16 threads per row");
+    const int tid = threadIdx.x;
+    if (tid >= 16 * BM) return;                    // (whole waves)
+    const int r = tid >> 4, i0 = 4 * (tid & 15);
     const bool valid = r < rows;
-    float *crow = Cs + r * CSW;
-    float l[NC], e[NC];
+    float4 *cp = (float4 *)(Cs + r * CSW + i0);
+    const float4 l4 = *cp;
+    const float l[4] = {l4.x, l4.y, l4.z, l4.w};
     float m = -INFINITY;
 #pragma unroll
-    for (int t = 0; t < NC; ++t) {
-        l[t] = crow[sub + TPR * t];
-        if (sub + TPR * t < A.W) m = fmaxf(m, l[t]);
-    }
-    m = rows_max(m, TPR);
-    float s = 0.f;
+    for (int t = 0; t < 4; ++t)
+        if (i0 + t < A.W) m = fmaxf(m, l[t]);
+    m = row16_max(m);
+    float e[4], s = 0.f;
 #pragma unroll
-    for (int t = 0; t < NC; ++t) {
-        e[t] = sub + TPR * t < A.W ? __expf(l[t] - m) : 0.f;
+    for (int t = 0; t < 4; ++t) {
+        e[t] = i0 + t < A.W ? __expf(l[t] - m) : 0.f;
         s += e[t];
     }
-    s = rows_sum(s, TPR);
+    s = row16_sum(s);
     const float lse = m + __logf(s), inv = 1.0f / s;
-    float wc = 0.f;
+    const float4 lr4 = *(const float4 *)(lr32 + i0);
+    const float lr[4] = {lr4.x, lr4.y, lr4.z, lr4.w};
+    float w[4], wc = 0.f;
 #pragma unroll
-    for (int t = 0; t < NC; ++t) {
-        const int i = sub + TPR * t;
-        const float w = valid ? e[t] * inv : 0.f;
-        if (w > 0.f) wc += w * (l[t] - lr32[i]);
-        crow[i] = w;
+    for (int t = 0; t < 4; ++t) {
+        w[t] = valid ? e[t] * inv : 0.f;
+        if (w[t] > 0.f) wc += w[t] * (l[t] - lr[t]);
     }
-    wc = rows_sum(wc, TPR);
-    if (sub == 0 && valid) {
+    *cp = make_float4(w[0], w[1], w[2], w[3]);
+    wc = row16_sum(wc);
+    if ((tid & 15) == 0 && valid) {
         acc.lse += (double)lse;
         acc.wc += (double)wc;                     // sum_i w_ji (l_ji - log rho_i)
         acc.rows += 1.0;
@@ -1926,7 +1928,7 @@ __host__ __device__ inline FacLds fac_lds(int K, int D, int Wp, int KCM, int BM,
 // in L2.  C: wave w takes the column tiles w, w + 8, .. of the BM x Wp tile.
 template <int BM, int KCM>
 __device__ __forceinline__ void fac_c_ph(const float *cb, int CBW, const float2 *ph, int L, int lo,
-                                         int W, int NT, int K, const float *rowf,
+                                         int W, int NT, int K,
                                          const float *lrs, float *Cs, int CSW) {
     constexpr int MT = BM / 16;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
@@ -1950,7 +1952,7 @@ __device__ __forceinline__ void fac_c_ph(const float *cb, int CBW, const float2 
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int row = 16 * m + 4 * g + q;
-            Cs[row * CSW + i] = cacc[q] * rowf[row] + lrs[i];
+            Cs[row * CSW + i] = cacc[q] + lrs[i];
         }
     }
 }
@@ -2122,8 +2124,8 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
     float *Cs = (float *)(smem + LY.off_cs);
     float2 *Us = (float2 *)(smem + LY.off_u);
     float2 *Sw = (float2 *)(smem + LY.off_sw);
-    float *rowf = (float *)(smem + LY.off_f);
-    float *rowu = rowf + BM;
+    float *rowu = (float *)(smem + LY.off_f) + BM;    // the row scales s_j
+    const float coef = (float)A.coef;
     float *lrs = (float *)(smem + LY.off_lr);
     // a (FP32) stored lane-major: entry e of lane l at [e][l], so the lanes' reads are
     // conflict-free
@@ -2284,15 +2286,13 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
                 cr += __shfl_xor(cr, o);
                 ci += __shfl_xor(ci, o);
             }
+            // c scaled by the row factor coef s_j: the C products then need no epilogue scaling
+            const float u = j < rows ? rsc[r] : 1.0f;
             if ((lane & (LPK - 1)) == 0) {
-                cb[j * LY.CBW + kl] = cr;
-                cb[j * LY.CBW + K + kl] = ci;
+                cb[j * LY.CBW + kl] = cr * (coef * u);
+                cb[j * LY.CBW + K + kl] = ci * (coef * u);
             }
-            if (lane == 0) {
-                const float u = j < rows ? rsc[r] : 1.0f;
-                rowf[j] = (float)A.coef * u;
-                rowu[j] = u;
-            }
+            if (lane == 0) rowu[j] = u;
         }
         lds_barrier();
         if (pf && wave >= 4) load_tile(tile + gridDim.x);
@@ -2316,11 +2316,11 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int row = 16 * cm + 4 * g + q;
-                Cs[row * LY.CSW + col] = cn < NT ? cacc[q] * rowf[row] + lrs[col] : 0.f;
+                Cs[row * LY.CSW + col] = cn < NT ? cacc[q] + lrs[col] : 0.f;
             }
           }
         } else if (use_ph) {
-            fac_c_ph<BM, KCM>(cb, LY.CBW, phs, A.L, A.lo, A.W, NT, K, rowf, lrs, Cs, LY.CSW);
+            fac_c_ph<BM, KCM>(cb, LY.CBW, phs, A.L, A.lo, A.W, NT, K, lrs, Cs, LY.CSW);
         } else {
             constexpr int MT = BM / 16;
             for (int p = wave; p < MT * NT; p += 8) {
@@ -2338,7 +2338,7 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int row = 16 * m + 4 * g + q;
-                    Cs[row * LY.CSW + col] = cacc[q] * rowf[row] + lrs[col];
+                    Cs[row * LY.CSW + col] = cacc[q] + lrs[col];
                 }
             }
         }
