@@ -2010,18 +2010,23 @@ __device__ __forceinline__ void u_mfma_ph(const float *Cs, int CSW, const float2
 }
 
 // U (BM x 2K) = w (BM x 64) . [Re E | Im E] for windows of at most 64 offsets, this wave's B
-// fragments in registers.  The sum over the window runs in a permuted order: lane (g, rl) takes
-// window index 16 g + kk at k-step kk (ereg[kk] = E2[16 g + kk][ucol]), so its A values are 16
-// consecutive posteriors of row rl, read as four 16-byte words.
+// fragments in registers, scaled by rowu (or without the row scale, which the M-step then
+// applies, when rowu is null).  The sum over the window
+// runs in a permuted order: lane (g, rl) takes window index 16 g + kk at k-step kk
+// (ereg[kk] = E2[16 g + kk][ucol]), so its A values are 16 consecutive posteriors of row rl, read
+// as four 16-byte words; with one row tile, even and odd k-steps accumulate in two chains.
 template <int BM>
 __device__ __forceinline__ void u_fac_reg(const float *Cs, int CSW, const float (&ereg)[16],
                                           int K, const float *rowu, float2 *Us, int ucol) {
     constexpr int MS = BM / 16;
     const int lane = threadIdx.x & 63, g = lane >> 4, rl = lane & 15;
     if ((ucol & ~15) >= 2 * K) return;             // this wave's U column tile is past 2K
-    f32x4 acc[MS];
+    constexpr int NCH = MS == 1 ? 2 : 1;           // accumulator chains per row tile
+    f32x4 acc[MS][NCH];
 #pragma unroll
-    for (int m = 0; m < MS; ++m) acc[m] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    for (int m = 0; m < MS; ++m)
+#pragma unroll
+        for (int h = 0; h < NCH; ++h) acc[m][h] = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int m = 0; m < MS; ++m) {
         const float4 *ar = (const float4 *)(Cs + (m * 16 + rl) * CSW + 16 * g);
@@ -2030,10 +2035,11 @@ __device__ __forceinline__ void u_fac_reg(const float *Cs, int CSW, const float 
         for (int t = 0; t < 4; ++t) a4[t] = ar[t];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[t].x, ereg[4 * t], acc[m], 0, 0, 0);
-            acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[t].y, ereg[4 * t + 1], acc[m], 0, 0, 0);
-            acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[t].z, ereg[4 * t + 2], acc[m], 0, 0, 0);
-            acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[t].w, ereg[4 * t + 3], acc[m], 0, 0, 0);
+            constexpr int o = NCH - 1;
+            acc[m][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[t].x, ereg[4 * t], acc[m][0], 0, 0, 0);
+            acc[m][o] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[t].y, ereg[4 * t + 1], acc[m][o], 0, 0, 0);
+            acc[m][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[t].z, ereg[4 * t + 2], acc[m][0], 0, 0, 0);
+            acc[m][o] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[t].w, ereg[4 * t + 3], acc[m][o], 0, 0, 0);
         }
     }
     if (ucol < 2 * K) {
@@ -2042,7 +2048,8 @@ __device__ __forceinline__ void u_fac_reg(const float *Cs, int CSW, const float 
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int row = m * 16 + 4 * g + q;
-                const float v = acc[m][q] * rowu[row];
+                float v = NCH == 2 ? acc[m][0][q] + acc[m][NCH - 1][q] : acc[m][0][q];
+                if (rowu) v *= rowu[row];
                 if (ucol < K)
                     Us[row * K + ucol].x = v;
                 else
@@ -2300,7 +2307,8 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
         // ---- C = [Re c | Im c] . E2^T on FP32 matrix cores -> l' = coef C / s_j + log rho
         if constexpr (!WIDE) {
           if (16 * cm < BM) {
-            f32x4 cacc = (f32x4){0.f, 0.f, 0.f, 0.f};
+            // even / odd k-steps in two chains (one for KCM = 32, which has no registers to spare)
+            f32x4 cacc = (f32x4){0.f, 0.f, 0.f, 0.f}, cacc1 = cacc;
             const float4 *arow = (const float4 *)(cb + (16 * cm + c) * LY.CBW + KCM * g);
             float4 a4[KCM / 4];
 #pragma unroll
@@ -2308,10 +2316,12 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
 #pragma unroll
             for (int t = 0; t < KCM / 4; ++t) {
                 cacc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[t].x, cfr[4 * t], cacc, 0, 0, 0);
-                cacc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[t].y, cfr[4 * t + 1], cacc, 0, 0, 0);
+                f32x4 &c1 = KCM <= 16 ? cacc1 : cacc;
+                c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[t].y, cfr[4 * t + 1], c1, 0, 0, 0);
                 cacc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[t].z, cfr[4 * t + 2], cacc, 0, 0, 0);
-                cacc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[t].w, cfr[4 * t + 3], cacc, 0, 0, 0);
+                c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[t].w, cfr[4 * t + 3], c1, 0, 0, 0);
             }
+            if (KCM <= 16) cacc += cacc1;
             const int col = 16 * cn + c;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -2352,8 +2362,9 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
         if (!(A.flags & PF_ACC_M)) continue;
         lds_barrier();
         tile_wsum<P, DPT>(A, LY.CSW, Cs, rows, acc);
+        // (two rows per wave: the M-step applies the row scale from its registers)
         if constexpr (!WIDE)
-            u_fac_reg<BM>(Cs, LY.CSW, ereg, K, rowu, Us, ucol);
+            u_fac_reg<BM>(Cs, LY.CSW, ereg, K, RPW == 2 ? nullptr : rowu, Us, ucol);
         else
             if (use_ph)
                 u_mfma_ph<BM>(Cs, LY.CSW, phs, A.L, A.lo, A.W, Wp, K, rowu, Us);
@@ -2365,7 +2376,11 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
             const int j = RPW * rg + r;
-            const float2 u = j < rows ? Us[j * K + kl] : make_float2(0.f, 0.f);
+            float2 u = j < rows ? Us[j * K + kl] : make_float2(0.f, 0.f);
+            if constexpr (!WIDE && RPW == 2) {            // (u_fac_reg left out the row scale)
+                u.x *= rsc[r];
+                u.y *= rsc[r];
+            }
 #pragma unroll
             for (int e = 0; e < EPL; ++e) {
                 const float2 v = vc[r].entry(e);
