@@ -1881,14 +1881,19 @@ __global__ __launch_bounds__(kThreads) void pass_wide_kernel(PassArgs A) {
 // Per row this costs 4D + 4KW flops instead of 4DW, no template exists, and the pass is a stream
 // over the rows.  Each wave owns fac_rpw rows of a tile of 8 fac_rpw rows and holds them in
 // registers (lane l: entries EPL l .. EPL l + EPL - 1, so D = 64 EPL with EPL = 8 for D = 512;
-// Q/EPL lanes share an angular frequency), while the next tile's rows load.  For D = 2048 in one
-// 16-bit plane (EPL = 16) a row is split over a pair of waves: wave w holds half h = w % 2 of the
-// rows of its row group w / 2 (virtual lane 64 h + lane: entries 16 (64 h + lane) ..).  c goes to LDS; C = [Re c | Im c] . [cos; sin] and
-// U = w [Re E | Im E] are FP32 matrix-core products against the phase table (fragments in
-// registers when Wp <= 64, streamed from L2 otherwise); the posteriors as in the other passes;
-// the M-step from the rows in registers, the eight waves' partial sums added in wave order into
-// per-entry FP64 accumulators (EPL = 8: the waves' FP32 partials summed by entry owners; EPL = 16:
-// the row groups add theirs in order into an FP64 copy of S in LDS).
+// Q/EPL lanes share an angular frequency), while the next tile's rows load (waves 0-3 issue their
+// loads at the top of a tile, waves 4-7 after the first barrier, so that the two halves' loads do
+// not queue behind each other).  For D = 2048 in one 16-bit plane (EPL = 16) a row is split over
+// a pair of waves: wave w holds half h = w % 2 of the rows of its row group w / 2 (virtual lane
+// 64 h + lane: entries 16 (64 h + lane) ..).  c (FMA chains, then a branch-free DPP sum over the
+// lanes of a frequency; scaled by the row factor coef s_j) goes to LDS;
+// C = [Re c | Im c] . [cos; sin] and U = w [Re E | Im E] are FP32 matrix-core products against
+// the phase table (fragments in registers when Wp <= 64, with a permuted k order so that the A
+// operands are 16-byte LDS words; otherwise from the LDS grid phase table or from L2); the
+// posteriors as in the other passes (tile_rows_short for Wp <= 64 without queries); the M-step
+// from the rows in registers, the eight waves' partial sums added in wave order into per-entry
+// FP64 accumulators (EPL = 8: the waves' FP32 partials summed by entry owners; EPL = 16: the row
+// groups add theirs in order into an FP64 copy of S in LDS).
 
 // rows per wave per tile: 2 for the 16-word row formats (FP32, bf16x3), 4 for one 16-bit plane
 __host__ __device__ constexpr int fac_rpw(int prec, int epl = 8) {

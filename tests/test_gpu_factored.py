@@ -1,6 +1,6 @@
 """The factored E(+M) pass (correlations through the per-frequency sums c_jk, an exact rewrite of
 the contraction; no template) against the FP64 oracle: teacher-forced steps on windowed and
-full-search shapes with one, two and four lanes per angular frequency and ragged row tails, every
+full-search shapes with one to 32 lanes per angular frequency and ragged row tails, every
 precision it supports; the large-image shape (D = 2048, 32 entries per lane, fp16 and bf16),
 including its full size; a windowed trajectory; the posterior queries and the adjoint."""
 import numpy as np
@@ -19,6 +19,8 @@ SHAPES = {
     "win16": (32, 16, 360, 24, 4099),      # the windowed workload's shape: W = 49
     "win8": (64, 8, 72, 6, 1001),          # one lane per frequency, W = 13
     "win32": (16, 32, 360, 40, 777),       # four lanes per frequency, W = 81 (L2 path)
+    "win128": (4, 128, 72, 6, 1001),       # 16 lanes per frequency: every DPP step of the sum
+    "win256": (2, 256, 72, 6, 517),        # 32 lanes per frequency: DPP steps and a shuffle
     "full": (32, 16, 60, None, 2050),      # full search, W = 60
 }
 
