@@ -105,7 +105,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--precision", default="fp32",
+                    choices=["fp32", "bf16x3", "fp16", "bf16", "fp64"])
     ap.add_argument("--correlation", action="store_true",
                     help="run the headline with the correlation GEMM against the rotated "
                          "templates instead of the factored E-step")
