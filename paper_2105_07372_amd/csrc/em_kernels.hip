@@ -23,6 +23,7 @@ namespace sem {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
@@ -812,7 +813,7 @@ __device__ __forceinline__ void tile_rows(const PassArgs &A, int CSW, typename P
 template <int BM, int DPT>
 __device__ __forceinline__ void tile_rows_short(const PassArgs &A, int CSW, float *Cs,
                                                 const float *lr32, int64_t r0, int rows,
-                                                PassAcc<DPT> &acc) {
+                                                PassAcc<DPT> &acc, uint8_t *wb = nullptr) {
     static_assert(16 * BM <= kThreads, "16 threads per row");
     const int tid = threadIdx.x;
     if (tid >= 16 * BM) return;                    // (whole waves)
@@ -843,6 +844,16 @@ __device__ __forceinline__ void tile_rows_short(const PassArgs &A, int CSW, floa
         if (w[t] > 0.f) wc += w[t] * (l[t] - lr[t]);
     }
     *cp = make_float4(w[0], w[1], w[2], w[3]);
+    if (wb) {                                      // bf16 hi + lo planes of the row (256 B)
+        bf16x4 h, lo;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            h[t] = (__bf16)w[t];
+            lo[t] = (__bf16)(w[t] - (float)h[t]);
+        }
+        *(bf16x4 *)(wb + r * 256 + 2 * i0) = h;
+        *(bf16x4 *)(wb + r * 256 + 128 + 2 * i0) = lo;
+    }
     wc = row16_sum(wc);
     if ((tid & 15) == 0 && valid) {
         acc.lse += (double)lse;
@@ -1909,11 +1920,12 @@ constexpr int kFacFlush16 = 8;                // ... with 16 entries per lane
 constexpr int kFacPhLds = 2048;               // grid phase table staged in LDS up to this L
 
 struct FacLds {
-    int CBW, CSW, off_cs, off_u, off_sw, off_f, off_lr, off_a, off_ph, total;
+    int CBW, CSW, off_cs, off_u, off_sw, off_f, off_lr, off_a, off_ph, off_wb, total;
 };
-// PHL: entries of the grid phase table kept in LDS (0: none)
+// PHL: entries of the grid phase table kept in LDS (0: none); WBF: bf16 hi + lo planes of the
+// posteriors (256 B per row) for the bf16 matrix-core U product
 __host__ __device__ inline FacLds fac_lds(int K, int D, int Wp, int KCM, int BM, int EPL = 8,
-                                          int PHL = 0) {
+                                          int PHL = 0, bool WBF = false) {
     FacLds l;
     l.CBW = 4 * KCM + 4;                       // [Re c | Im c | 0 ..], conflict-free A reads
     l.CSW = (Wp > 64 ? Wp : 64) + 4;           // columns past Wp stay zero (register U path)
@@ -1924,7 +1936,8 @@ __host__ __device__ inline FacLds fac_lds(int K, int D, int Wp, int KCM, int BM,
     l.off_lr = l.off_f + 2 * BM * 4;
     l.off_a = align_up(l.off_lr + Wp * 4, 16);
     l.off_ph = align_up(l.off_a + D * 8, 16);
-    l.total = l.off_ph + PHL * 8;
+    l.off_wb = align_up(l.off_ph + PHL * 8, 16);
+    l.total = l.off_wb + (WBF ? BM * 256 : 0);
     return l;
 }
 
@@ -2063,6 +2076,45 @@ __device__ __forceinline__ void u_fac_reg(const float *Cs, int CSW, const float 
     }
 }
 
+// The same U product in bf16 hi + lo on matrix cores (three 16x16x32 products per k-step, FP32
+// accumulation, the lo x lo term left out): A from the bf16 planes of the posteriors (row rl,
+// window indices 32 s + 8 g .. + 7), B = hi / lo of E2[32 s + 8 g + t][ucol], t = 0 .. 7.
+__device__ __forceinline__ void u_fac_bf(const uint8_t *wb, const bf16x8 (&bh)[2],
+                                         const bf16x8 (&bl)[2], int K, float2 *Us, int ucol) {
+    const int lane = threadIdx.x & 63, g = lane >> 4, rl = lane & 15;
+    if ((ucol & ~15) >= 2 * K) return;             // this wave's U column tile is past 2K
+    f32x4 acc0 = (f32x4){0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
+    const uint8_t *ar = wb + rl * 256 + 16 * g;
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
+        const bf16x8 AH = *(const bf16x8 *)(ar + 64 * st);
+        const bf16x8 AL = *(const bf16x8 *)(ar + 128 + 64 * st);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AH, bh[st], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AL, bh[st], acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AH, bl[st], acc0, 0, 0, 0);
+    }
+    if (ucol < 2 * K) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int row = 4 * g + q;
+            const float v = acc0[q] + acc1[q];
+            if (ucol < K)
+                Us[row * K + ucol].x = v;
+            else
+                Us[row * K + ucol - K].y = v;
+        }
+    }
+}
+
+// hi and lo bf16x8 of eight FP32 values
+__device__ __forceinline__ void split_bf16x8(const float (&x)[8], bf16x8 &h, bf16x8 &l) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        h[t] = (__bf16)x[t];
+        l[t] = (__bf16)(x[t] - (float)h[t]);
+    }
+}
+
 // Words of one stored row for lane l (entries EPL l .. EPL l + EPL - 1): FP32 2 EPL words
 // (re, im per entry); bf16x3 EPL hi words then EPL lo words; fp16 / bf16 EPL words.
 template <int P, int EPL = 8>
@@ -2116,6 +2168,10 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
     constexpr bool HR = EPL == 16;                 // a row over a pair of waves
     constexpr int NVL = HR ? 128 : 64;             // virtual lanes of a row: D = NVL EPL
     constexpr int RPW = fac_rpw(P, EPL), BM = fac_bm(P, EPL), DPT = NVL * EPL / kThreads;
+    // bf16x3 storage, windows up to 64, 2K up to 64: the C and U products in bf16 hi + lo on
+    // matrix cores (c and the posteriors kept as bf16 hi + lo planes in LDS)
+    constexpr bool BFX = P == P_BF16X3 && !WIDE && KCM == 16;
+    static_assert(!BFX || BM == 16, "one 16-row tile");
     if ((A.flags & PF_CHECK_STOP) && *A.stopped) return;
 
     extern __shared__ __align__(16) uint8_t smem[];
@@ -2127,7 +2183,8 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
     const int vl = 64 * hh + lane;                 // this lane's place in the row
     // long windows on the grid: the phase factors come from an LDS copy of the grid phase table
     const bool use_ph = WIDE && A.grid && A.L <= kFacPhLds;
-    const FacLds LY = fac_lds(K, D, Wp, KCM, BM, EPL, use_ph ? A.L : 0);
+    const FacLds LY = fac_lds(K, D, Wp, KCM, BM, EPL, use_ph ? A.L : 0, BFX);
+    uint8_t *wb = smem + LY.off_wb;                // (BFX) bf16 planes of the posteriors
     float2 *phs = (float2 *)(smem + LY.off_ph);
     if (use_ph)
         for (int m = tid; m < A.L; m += kThreads)
@@ -2155,35 +2212,58 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
     float lpk_f[4];                                // the DPP steps of the LPK-lane sums
 #pragma unroll
     for (int t = 0; t < 4; ++t) lpk_f[t] = LPK > (1 << t) ? 1.f : 0.f;
-    // columns 2K .. 4 KCM - 1 of the c rows stay zero for the whole pass
-    for (int x = tid; x < BM * (4 * KCM - 2 * K); x += kThreads) {
-        const int j = x / (4 * KCM - 2 * K);
-        cb[j * LY.CBW + 2 * K + x % (4 * KCM - 2 * K)] = 0.f;
+    // columns 2K .. 4 KCM - 1 of the c rows stay zero for the whole pass (BFX: the c rows are a
+    // bf16 hi plane of 64 entries followed by a lo plane, zero past 2K in both)
+    if constexpr (BFX) {
+        for (int x = tid; x < BM * LY.CBW; x += kThreads) cb[x] = 0.f;
+    } else {
+        for (int x = tid; x < BM * (4 * KCM - 2 * K); x += kThreads) {
+            const int j = x / (4 * KCM - 2 * K);
+            cb[j * LY.CBW + 2 * K + x % (4 * KCM - 2 * K)] = 0.f;
+        }
     }
     __syncthreads();
     // C product: wave w computes rows 16 (w >> 2) .. of window tile (w & 3) (Wp <= 64); the sum
     // over [Re c | Im c] runs in a permuted order (lane group g takes columns KCM g .. KCM g +
     // KCM - 1, read as 16-byte words), so its B fragments are E2[16 n + c][KCM g + kk] (zero past
     // 2K)
-    float cfr[KCM];
+    float cfr[BFX ? 1 : KCM];
     const int cm = wave >> 2, cn = wave & 3;       // (16-row tiles: waves 0-3 only)
-    if constexpr (!WIDE) {
+    if constexpr (!WIDE && !BFX) {
 #pragma unroll
         for (int kk = 0; kk < KCM; ++kk) {
             const int col = KCM * g + kk, i = 16 * cn + c;
             cfr[kk] = (col < 2 * K && i < Wp) ? A.E2[(int64_t)i * 2 * K + col] : 0.f;
         }
     }
+    // BFX: B fragments of C (k-step s: E2[16 cn + c][32 s + 8 g + t]) and of U
+    // (E2[32 s + 8 g + t][ucol]), hi and lo
+    bf16x8 cbh[BFX ? 2 : 1], cbl[BFX ? 2 : 1], ubh[BFX ? 2 : 1], ubl[BFX ? 2 : 1];
     // U product: wave w computes U columns 16 (w ^ 4) + c over 16 k-steps (Wp <= 64): for
     // 2K <= 64 the upper four waves, while wave 0 takes the W column sums; window index
     // 16 g + kk at k-step kk (u_fac_reg)
     const int ucol = (wave ^ 4) * 16 + c;
-    float ereg[16];
-    if constexpr (!WIDE) {
+    float ereg[BFX ? 1 : 16];
+    if constexpr (!WIDE && !BFX) {
 #pragma unroll
         for (int kk = 0; kk < 16; ++kk) {
             const int i = 16 * g + kk;
             ereg[kk] = (i < Wp && ucol < 2 * K) ? A.E2[(int64_t)i * 2 * K + ucol] : 0.f;
+        }
+    }
+    if constexpr (BFX) {
+#pragma unroll
+        for (int st = 0; st < 2; ++st) {
+            float xc[8], xu[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int kc = 32 * st + 8 * g + t, ic = 16 * cn + c;
+                xc[t] = (kc < 2 * K && ic < Wp) ? A.E2[(int64_t)ic * 2 * K + kc] : 0.f;
+                const int iu = 32 * st + 8 * g + t;
+                xu[t] = (iu < Wp && ucol < 2 * K) ? A.E2[(int64_t)iu * 2 * K + ucol] : 0.f;
+            }
+            split_bf16x8(xc, cbh[st], cbl[st]);
+            split_bf16x8(xu, ubh[st], ubl[st]);
         }
     }
 
@@ -2301,8 +2381,18 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
             // c scaled by the row factor coef s_j: the C products then need no epilogue scaling
             const float u = j < rows ? rsc[r] : 1.0f;
             if ((lane & (LPK - 1)) == 0) {
-                cb[j * LY.CBW + kl] = cr * (coef * u);
-                cb[j * LY.CBW + K + kl] = ci * (coef * u);
+                const float xr = cr * (coef * u), xi = ci * (coef * u);
+                if constexpr (BFX) {
+                    __bf16 *ch = (__bf16 *)(cb + j * LY.CBW);     // hi [0, 64), lo [64, 128)
+                    const __bf16 hr = (__bf16)xr, hi_ = (__bf16)xi;
+                    ch[kl] = hr;
+                    ch[K + kl] = hi_;
+                    ch[64 + kl] = (__bf16)(xr - (float)hr);
+                    ch[64 + K + kl] = (__bf16)(xi - (float)hi_);
+                } else {
+                    cb[j * LY.CBW + kl] = xr;
+                    cb[j * LY.CBW + K + kl] = xi;
+                }
             }
             if (lane == 0) rowu[j] = u;
         }
@@ -2310,7 +2400,26 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
         if (pf && wave >= 4) load_tile(tile + gridDim.x);
 
         // ---- C = [Re c | Im c] . E2^T on FP32 matrix cores -> l' = coef C / s_j + log rho
-        if constexpr (!WIDE) {
+        if constexpr (BFX) {
+          if (wave < 4) {
+            f32x4 cacc = (f32x4){0.f, 0.f, 0.f, 0.f}, cacc1 = cacc;
+            const uint8_t *arow = (const uint8_t *)(cb + c * LY.CBW) + 16 * g;
+#pragma unroll
+            for (int st = 0; st < 2; ++st) {
+                const bf16x8 AH = *(const bf16x8 *)(arow + 64 * st);
+                const bf16x8 AL = *(const bf16x8 *)(arow + 128 + 64 * st);
+                cacc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AH, cbh[st], cacc, 0, 0, 0);
+                cacc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AL, cbh[st], cacc1, 0, 0, 0);
+                cacc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AH, cbl[st], cacc, 0, 0, 0);
+            }
+            const int col = 16 * cn + c;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = 4 * g + q;
+                Cs[row * LY.CSW + col] = cn < NT ? cacc[q] + cacc1[q] + lrs[col] : 0.f;
+            }
+          }
+        } else if constexpr (!WIDE) {
           if (16 * cm < BM) {
             // even / odd k-steps in two chains (one for KCM = 32, which has no registers to spare)
             f32x4 cacc = (f32x4){0.f, 0.f, 0.f, 0.f}, cacc1 = cacc;
@@ -2360,15 +2469,30 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
         lds_barrier();
 
         // ---- a4 + a5
-        if (!WIDE && !(A.flags & (PF_QUERY | PF_LOAD_LSE)))
-            tile_rows_short<BM, DPT>(A, LY.CSW, Cs, lrs, r0, rows, acc);
+        const bool short_rows = !WIDE && !(A.flags & (PF_QUERY | PF_LOAD_LSE));
+        if (short_rows)
+            tile_rows_short<BM, DPT>(A, LY.CSW, Cs, lrs, r0, rows, acc, BFX ? wb : nullptr);
         else
             tile_rows<P, BM, DPT>(A, LY.CSW, Cs, lrs, r0, rows, acc);
         if (!(A.flags & PF_ACC_M)) continue;
         lds_barrier();
+        if constexpr (BFX) {
+            if (!short_rows) {                         // the bf16 planes from the FP32 posteriors
+                for (int x = tid; x < BM * 64; x += kThreads) {
+                    const int r = x >> 6, i = x & 63;
+                    const float w = Cs[r * LY.CSW + i];
+                    const __bf16 h = (__bf16)w;
+                    ((__bf16 *)(wb + r * 256))[i] = h;
+                    ((__bf16 *)(wb + r * 256 + 128))[i] = (__bf16)(w - (float)h);
+                }
+                lds_barrier();
+            }
+        }
         tile_wsum<P, DPT>(A, LY.CSW, Cs, rows, acc);
         // (two rows per wave: the M-step applies the row scale from its registers)
-        if constexpr (!WIDE)
+        if constexpr (BFX)
+            u_fac_bf(wb, ubh, ubl, K, Us, ucol);
+        else if constexpr (!WIDE)
             u_fac_reg<BM>(Cs, LY.CSW, ereg, K, RPW == 2 ? nullptr : rowu, Us, ucol);
         else
             if (use_ph)
@@ -2977,7 +3101,8 @@ bool fac_plan(int prec, int D, int Q, int K, int Wp, int gridL, size_t lds_max, 
     if (!kcm || !find_fac(prec, wide, kcm, epl)) return false;
     const int bm = fac_bm(prec, epl);
     const int phl = (wide && gridL > 0 && gridL <= kFacPhLds) ? gridL : 0;
-    const size_t b = (size_t)fac_lds(K, D, Wp, kcm, bm, epl, phl).total;
+    const bool wbf = prec == P_BF16X3 && !wide && kcm == 16;
+    const size_t b = (size_t)fac_lds(K, D, Wp, kcm, bm, epl, phl, wbf).total;
     if (b > lds_max) return false;
     *WIDE = wide;
     *KCM = kcm;
