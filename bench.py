@@ -277,8 +277,11 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         # the arithmetic: the factored E-step computes in FP32 whatever the observations' storage
+        # the arithmetic: the factored E-step forms c_jk in FP32 whatever the storage, and its
+        # matrix-core products in bf16 hi + lo for bf16x3 storage, else in FP32
         "dtype": ({"bf16x3": "bf16", "fp16": "fp16", "fp32": "fp32", "fp64": "fp64",
-                   "bf16": "bf16"}[args.precision] if args.correlation else "fp32"),
+                   "bf16": "bf16"}[args.precision] if args.correlation
+                  else ("bf16" if args.precision == "bf16x3" else "fp32")),
         "data": "synthetic",
         "config": {"workload": f"windowed Synch-EM N={w.N} D={w.D} (K={w.K},Q={w.Q}) L={w.L} "
                                f"W={W} gamma={w.gamma} learned prior, {args.precision}"
