@@ -235,18 +235,33 @@ __global__ __launch_bounds__(kSyncThreads) void relrot_tile_kernel(const float2 
 
 // One projected power iteration: 4 rows per workgroup, 64 lanes per row summing j = lane,
 // lane + 64, .. in FP64, then a butterfly over the wave; z_out = y / |y| (z_in kept if y = 0).
+// PHL: the L phases are first copied to LDS (L <= kPpmPhLds), so the per-entry lookups are LDS
+// reads rather than scattered global ones.
+constexpr int kPpmPhLds = 2048;
+template <bool PHL>
 __global__ __launch_bounds__(kSyncThreads) void ppm_kernel(const int *rel, int P, int L,
                                                            const double2 *ph,
                                                            const double2 *z_in,
                                                            double2 *z_out) {
+    __shared__ double2 phs[PHL ? kPpmPhLds : 1];
+    if constexpr (PHL) {
+        for (int m = threadIdx.x; m < L; m += kSyncThreads) phs[m] = ph[m];
+        __syncthreads();
+    }
     const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= P) return;                                     // whole waves leave together
     double yr = 0.0, yi = 0.0;
+#pragma unroll 4
     for (int j = lane; j < P; j += 64) {
-        int m = rel[(int64_t)i * P + j] % L;
-        if (m < 0) m += L;
-        const double2 h = ph[m], z = z_in[j];
+        int m = rel[(int64_t)i * P + j];
+        if (m < 0 || m >= L) {                              // (reduced mod L)
+            m %= L;
+            if (m < 0) m += L;
+        }
+        double2 h;
+        if constexpr (PHL) h = phs[m]; else h = ph[m];
+        const double2 z = z_in[j];
         yr += h.x * z.x - h.y * z.y;
         yi += h.x * z.y + h.y * z.x;
     }
@@ -527,8 +542,12 @@ hipError_t launch_ppm(const int *rel, int P, int L, const double2 *ph, double2 *
                       int iters, double *theta, hipStream_t s) {
     hipLaunchKernelGGL(ones_kernel, dim3((P + 255) / 256), dim3(256), 0, s, z0, P);
     for (int it = 0; it < iters; ++it) {
-        hipLaunchKernelGGL(ppm_kernel, dim3((P + 3) / 4), dim3(kSyncThreads), 0, s, rel, P, L,
-                           ph, (it & 1) ? z1 : z0, (it & 1) ? z0 : z1);
+        if (L <= kPpmPhLds)
+            hipLaunchKernelGGL(ppm_kernel<true>, dim3((P + 3) / 4), dim3(kSyncThreads), 0, s, rel,
+                               P, L, ph, (it & 1) ? z1 : z0, (it & 1) ? z0 : z1);
+        else
+            hipLaunchKernelGGL(ppm_kernel<false>, dim3((P + 3) / 4), dim3(kSyncThreads), 0, s,
+                               rel, P, L, ph, (it & 1) ? z1 : z0, (it & 1) ? z0 : z1);
     }
     hipLaunchKernelGGL(angle_kernel, dim3((P + 255) / 256), dim3(256), 0, s,
                        (iters & 1) ? z1 : z0, P, theta);

@@ -67,6 +67,20 @@ def test_ppm_matches_oracle(gpu):
         assert np.abs(np.angle(np.exp(1j * (th - to)))).max() <= 1e-9, iters
 
 
+@pytest.mark.parametrize("L", [72, 3000])          # 3000: the phases read from global memory
+def test_ppm_any_integer_relative_rotations(gpu, L):
+    """Relative rotations are taken mod L: any integers, negative and past L included, give the
+    oracle's iterates."""
+    import torch
+    from paper_2105_07372_amd import ppm
+    rng = np.random.default_rng(7)
+    rel = rng.integers(-2 * L, 2 * L, size=(300, 300)).astype(np.int32)
+    for iters in (1, 5):
+        th = ppm(torch.from_numpy(rel).to(gpu), L, iters).cpu().numpy()
+        to = oracle.ppm(rel, L, iters)
+        assert np.abs(np.angle(np.exp(1j * (th - to)))).max() <= 1e-9, (L, iters)
+
+
 @pytest.mark.parametrize("K,Q,N,P", [(8, 8, 3001, 200), (16, 8, 1000, 1000), (4, 2, 517, 37),
                                      (32, 32, 600, 100)])   # the last: rows too long for LDS
 def test_nearest_neighbours(gpu, K, Q, N, P):
