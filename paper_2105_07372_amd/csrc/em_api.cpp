@@ -91,6 +91,13 @@ em_status fail(em_ctx *c, em_status s, const std::string &msg) {
     return s;
 }
 
+// Waits for a call's work on its stream whatever happened (the call's scratch is freed on
+// return) and keeps the first error.
+hipError_t finish(hipError_t e, hipStream_t s) {
+    const hipError_t se = hipStreamSynchronize(s);
+    return e != hipSuccess ? e : se;
+}
+
 #define HIPCHK(ctx, call)                                                                      \
     do {                                                                                       \
         hipError_t e_ = (call);                                                                \
@@ -847,7 +854,7 @@ em_status em_learn_prior(const int32_t *err_dev, int64_t n, int32_t L, int32_t l
     e = hipMemcpyAsync(cnt, h.data(), (size_t)L * 8, hipMemcpyHostToDevice, s);
     if (e == hipSuccess && n > 0) e = launch_histogram(err_dev, n, L, cnt, s);
     if (e == hipSuccess) e = hipMemcpyAsync(h.data(), cnt, (size_t)L * 8, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    e = finish(e, s);
     (void)hipFree(cnt);
     if (e != hipSuccess) return fail(nullptr, EM_EDEVICE, std::string("histogram: ") + hipGetErrorString(e));
     const int lom = ((lo % L) + L) % L;
@@ -927,7 +934,7 @@ em_status em_relative_rotations(const void *obs_dev, int64_t P, int32_t K, int32
     hipError_t e = hipMemcpyAsync(Bd, B.data(), B.size() * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = launch_relrot((const float2 *)obs_dev, (int)P, K, Q, L, Bd, rel_dev, gap, dot, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    e = finish(e, s);
     return hip_status(e, "relative rotations");
 }
 
@@ -952,7 +959,7 @@ em_status em_ppm(const int32_t *rel_dev, int64_t P, int32_t L, int32_t iters, do
     hipError_t e = hipMemcpyAsync(phd, ph.data(), ph.size() * sizeof(double2),
                                   hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = launch_ppm(rel_dev, (int)P, L, phd, z0, z1, iters, theta_dev, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    e = finish(e, s);
     return hip_status(e, "power method");
 }
 
@@ -972,7 +979,7 @@ em_status em_nearest(const void *obs_dev, int64_t N, int32_t K, int32_t Q, int64
     if (!buf.get((void **)&nrm, (size_t)P * sizeof(float)) || (!gap && !buf.get((void **)&gap, (size_t)N * sizeof(float))))
         return fail(nullptr, EM_ENOMEM, "hipMalloc failed");
     hipError_t e = launch_nearest((const float2 *)obs_dev, N, P, K * Q, nrm, nn_dev, gap, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    e = finish(e, s);
     return hip_status(e, "nearest neighbours");
 }
 
@@ -1000,7 +1007,7 @@ em_status em_sync_match(const void *obs_dev, int64_t N, int32_t K, int32_t Q, in
     if ((st = em_ppm(rel, P, L, iters, phi, stream)) != EM_OK) return st;
     if ((st = em_nearest(obs_dev, N, K, Q, P, nn, nullptr, stream)) != EM_OK) return st;
     hipError_t e = launch_gather(phi, P, nn, N, theta_dev, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    e = finish(e, s);
     return hip_status(e, "gather");
 }
 
@@ -1013,7 +1020,7 @@ em_status em_align(const void *obs_dev, int64_t N, int32_t K, int32_t Q, const d
         return fail(nullptr, EM_EINVAL, "obs_dev, theta_dev and out_dev are required");
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = launch_align((const float2 *)obs_dev, N, K, Q, theta_dev, (float2 *)out_dev, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    e = finish(e, s);
     return hip_status(e, "align");
 }
 
@@ -1035,7 +1042,7 @@ em_status em_aligned_mean(const void *obs_dev, int64_t N, int32_t K, int32_t Q,
     hipError_t e = launch_aligned_colsum((const float2 *)obs_dev, N, K, Q, theta_dev, part, G, s);
     if (e == hipSuccess) e = launch_reduce(part, G, 2 * D, sum, s);
     if (e == hipSuccess) e = launch_scale(sum, mean_dev, 2 * D, 1.0 / (double)N, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    e = finish(e, s);
     return hip_status(e, "aligned mean");
 }
 
@@ -1048,7 +1055,7 @@ em_status em_error_bins(const double *theta_hat_dev, const double *theta_dev, in
     if (L < 1 || L > 16384) return fail(nullptr, EM_EINVAL, "L must be in [1, 16384]");
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = launch_error_bins(theta_hat_dev, theta_dev, N, L, lc, bins_dev, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    e = finish(e, s);
     return hip_status(e, "error bins");
 }
 
