@@ -2938,7 +2938,7 @@ bool pass_variant_exists(int prec, int BM, int WM, int LD) {
 static const char *kPrecName[] = {"f64", "f32", "bf16x3", "f16", "bf16"};
 
 const char *pass_kernel_name(int prec, int BM, int WM, int LD) {
-    static char buf[64];
+    static thread_local char buf[64];   // (per thread: callers copy it out)
     snprintf(buf, sizeof buf, "pass_kernel<%s,BM=%d,WM=%d,%s>", kPrecName[prec], BM, WM,
              LD ? "dma" : "reg");
     return buf;
@@ -3015,7 +3015,7 @@ hipError_t pass_ks_setup(int prec, int BM, int NT, int KSS, size_t lds, int *blo
 }
 
 const char *pass_ks_name(int prec, int BM, int NT, int KSS) {
-    static char buf[64];
+    static thread_local char buf[64];   // (per thread: callers copy it out)
     snprintf(buf, sizeof buf, "pass_ks_kernel<%s,BM=%d,NT=%d,KSS=%d>", kPrecName[prec], BM, NT,
              KSS);
     return buf;
@@ -3066,7 +3066,7 @@ hipError_t pass_wide_setup(int prec, int NTW, int UR, size_t lds, int *blocks_pe
 }
 
 const char *pass_wide_name(int prec, int NTW, int UR) {
-    static char buf[64];
+    static thread_local char buf[64];   // (per thread: callers copy it out)
     snprintf(buf, sizeof buf, "pass_wide_kernel<%s,BM=%d,NTW=%d,UR=%d>", kPrecName[prec],
              kWideBM, NTW, UR);
     return buf;
@@ -3131,7 +3131,7 @@ hipError_t pass_fac_setup(int prec, int WIDE, int KCM, int EPL, size_t lds, int 
 }
 
 const char *pass_fac_name(int prec, int WIDE, int KCM, int EPL) {
-    static char buf[64];
+    static thread_local char buf[64];   // (per thread: callers copy it out)
     snprintf(buf, sizeof buf, "pass_fac_kernel<%s,BM=%d,%s,KC=%d%s>", kPrecName[prec],
              fac_bm(prec, EPL), WIDE ? "L2" : "reg", KCM, EPL == 16 ? ",E16" : "");
     return buf;
