@@ -104,7 +104,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    # untimed EM iterations before each timed run: a few milliseconds of work bring the GPU
+    # from idle to its sustained clocks (5 warm-up steps left the first timed run ~10% slow)
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--precision", default="fp32",
                     choices=["fp32", "bf16x3", "fp16", "bf16", "fp64"])
     ap.add_argument("--correlation", action="store_true",
@@ -201,9 +203,8 @@ def main():
         w2 = wl.WORKLOADS["c2"]
         ef = EM(obs, K=w.K, Q=w.Q, L=w.L, sigma2=s2, precision="fp32", timing=True,
                 a0=wl.random_init(w2, 0))
-        df, pf, _ = time_em(ef, max(5, args.steps // 5), 2,
-                            (wl.random_init(w2, 0), np.full(w.L, 1.0 / w.L), 0))
-        nsteps = max(5, args.steps // 5)
+        nsteps, nwarm = max(5, args.steps // 5), max(2, args.warmup // 10)
+        df, pf, _ = time_em(ef, nsteps, nwarm, (wl.random_init(w2, 0), np.full(w.L, 1.0 / w.L), 0))
         baseline = {"workload": "plain full-search EM, FP32 MFMA, same N, D, all L=360 "
                                 "rotations, uniform prior",
                     "iter_per_s": nsteps / df, "obs_rot_per_s": nsteps / df * w.N * w.L,
@@ -212,7 +213,7 @@ def main():
         log(f"bench: full search fp32 {baseline['iter_per_s']:.1f} it/s")
         ef = EM(obs, K=w.K, Q=w.Q, L=w.L, sigma2=s2, precision="fp32", timing=True,
                 a0=wl.random_init(w2, 0), factored=True)
-        df, pf, _ = time_em(ef, nsteps, 2, (wl.random_init(w2, 0), np.full(w.L, 1.0 / w.L), 0))
+        df, pf, _ = time_em(ef, nsteps, nwarm, (wl.random_init(w2, 0), np.full(w.L, 1.0 / w.L), 0))
         variants["full_search_factored_fp32"] = {"iter_per_s": nsteps / df, "pass_us": pf * 1e3,
                                                  "kernel": ef.info()["kernel"]}
         ef.close()
