@@ -1914,7 +1914,7 @@ __host__ __device__ constexpr int fac_rpw(int prec, int epl = 8) {
 __host__ __device__ constexpr int fac_bm(int prec, int epl = 8) {
     return (epl == 16 ? 4 : 8) * fac_rpw(prec, epl);
 }
-constexpr int kFacFlush = 4;                  // tiles summed in FP32 before the FP64 flush
+constexpr int kFacFlush = 16;                 // tiles summed in FP32 before the FP64 flush
 constexpr int kFacFlush16 = 8;                // ... with 16 entries per lane
 
 constexpr int kFacPhLds = 2048;               // grid phase table staged in LDS up to this L
