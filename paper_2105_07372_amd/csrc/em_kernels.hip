@@ -813,7 +813,8 @@ __device__ __forceinline__ void tile_rows(const PassArgs &A, int CSW, typename P
 template <int BM, int DPT>
 __device__ __forceinline__ void tile_rows_short(const PassArgs &A, int CSW, float *Cs,
                                                 const float *lr32, int64_t r0, int rows,
-                                                PassAcc<DPT> &acc, uint8_t *wb = nullptr) {
+                                                PassAcc<DPT> &acc, uint8_t *wb = nullptr,
+                                                const float4 *lrv = nullptr) {
     static_assert(16 * BM <= kThreads, "16 threads per row");
     const int tid = threadIdx.x;
     if (tid >= 16 * BM) return;                    // (whole waves)
@@ -835,7 +836,7 @@ __device__ __forceinline__ void tile_rows_short(const PassArgs &A, int CSW, floa
     }
     s = row16_sum(s);
     const float lse = m + __logf(s), inv = 1.0f / s;
-    const float4 lr4 = *(const float4 *)(lr32 + i0);
+    const float4 lr4 = lrv ? *lrv : *(const float4 *)(lr32 + i0);
     const float lr[4] = {lr4.x, lr4.y, lr4.z, lr4.w};
     float w[4], wc = 0.f;
 #pragma unroll
@@ -2223,6 +2224,18 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
         }
     }
     __syncthreads();
+    // two-row formats, short windows: values that stay fixed for the pass held in registers (the
+    // lane's coefficients, its C-epilogue log-prior, its four posterior-step log-priors)
+    constexpr bool kHold = !HR && !WIDE && RPW == 2;
+    float2 ahold[kHold ? EPL : 1];
+    float4 lrhold = make_float4(0.f, 0.f, 0.f, 0.f);
+    float lrc = 0.f;
+    if constexpr (kHold) {
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) ahold[e] = as[e * NVL + vl];
+        if (tid < 16 * BM) lrhold = *(const float4 *)(lrs + 4 * (tid & 15));
+        if ((wave & 3) < NT) lrc = lrs[16 * (wave & 3) + c];
+    }
     // C product: wave w computes rows 16 (w >> 2) .. of window tile (w & 3) (Wp <= 64); the sum
     // over [Re c | Im c] runs in a permuted order (lane group g takes columns KCM g .. KCM g +
     // KCM - 1, read as 16-byte words), so its B fragments are E2[16 n + c][KCM g + kk] (zero past
@@ -2354,7 +2367,10 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
         // ---- c_jk for this wave's rows; row factors.  EPL = 8: the lane's coefficients are read
         // from LDS once per tile, ahead of the rows
         float2 areg[HR ? 1 : EPL];
-        if constexpr (!HR) {
+        if constexpr (kHold) {
+#pragma unroll
+            for (int e = 0; e < EPL; ++e) areg[e] = ahold[e];
+        } else if constexpr (!HR) {
 #pragma unroll
             for (int e = 0; e < EPL; ++e) areg[e] = as[e * NVL + vl];
         }
@@ -2416,7 +2432,7 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int row = 4 * g + q;
-                Cs[row * LY.CSW + col] = cn < NT ? cacc[q] + cacc1[q] + lrs[col] : 0.f;
+                Cs[row * LY.CSW + col] = cn < NT ? cacc[q] + cacc1[q] + (kHold ? lrc : lrs[col]) : 0.f;
             }
           }
         } else if constexpr (!WIDE) {
@@ -2440,7 +2456,7 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int row = 16 * cm + 4 * g + q;
-                Cs[row * LY.CSW + col] = cn < NT ? cacc[q] + lrs[col] : 0.f;
+                Cs[row * LY.CSW + col] = cn < NT ? cacc[q] + (kHold ? lrc : lrs[col]) : 0.f;
             }
           }
         } else if (use_ph) {
@@ -2471,7 +2487,8 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
         // ---- a4 + a5
         const bool short_rows = !WIDE && !(A.flags & (PF_QUERY | PF_LOAD_LSE));
         if (short_rows)
-            tile_rows_short<BM, DPT>(A, LY.CSW, Cs, lrs, r0, rows, acc, BFX ? wb : nullptr);
+            tile_rows_short<BM, DPT>(A, LY.CSW, Cs, lrs, r0, rows, acc, BFX ? wb : nullptr,
+                                     kHold ? &lrhold : nullptr);
         else
             tile_rows<P, BM, DPT>(A, LY.CSW, Cs, lrs, r0, rows, acc);
         if (!(A.flags & PF_ACC_M)) continue;
