@@ -413,3 +413,97 @@ def test_map_objective_is_stationary_at_em_fixed_point():
         e = np.zeros(len(eta))
         e[i] = h
         assert abs(J(a, eta + e) - J(a, eta - e)) / (2 * h) <= 1e-5 * max(1.0, gamma)
+
+
+# ---------------------------------------------------------------- argmax and top-two margin (eq. 15)
+
+def _argmax_margin_by_definition(w):
+    """The most probable rotation and the probability gap, read off each row by a plain scan:
+    the first index whose weight is not exceeded by any other (the lowest index wins a tie),
+    and that weight minus the largest weight at any other index (0 when the maximum is shared;
+    with one rotation there is no other index and the gap is the weight itself)."""
+    idx, gap = [], []
+    for row in np.asarray(w, dtype=np.float64):
+        best = 0
+        for i in range(1, len(row)):
+            if row[i] > row[best]:
+                best = i
+        other = [row[i] for i in range(len(row)) if i != best]
+        idx.append(best)
+        gap.append(row[best] - max(other) if other else row[best])
+    return np.array(idx), np.array(gap)
+
+
+def _argmax_margin_failures(fn):
+    """Names of the checks that ``fn`` fails; an empty list means it is a correct argmax/margin."""
+    fails = []
+    rng = np.random.default_rng(7)
+
+    def agree(name, w):
+        i1, g1 = fn(w)
+        i2, g2 = _argmax_margin_by_definition(w)
+        if not (np.array_equal(np.asarray(i1), i2) and np.allclose(g1, g2, rtol=0, atol=1e-15)):
+            fails.append(name)
+
+    # rows of a softmax (what the E-step produces), distinct entries almost surely
+    x = rng.standard_normal((40, 9))
+    agree("random rows", np.exp(x) / np.exp(x).sum(axis=1, keepdims=True))
+    # ties at the maximum: lowest index, zero gap
+    agree("two-way tie", np.array([[0.1, 0.4, 0.1, 0.4], [0.45, 0.1, 0.0, 0.45]]))
+    agree("uniform row", np.full((3, 5), 0.2))
+    # one rotation only (W = 1): the gap is the weight itself
+    agree("single rotation", np.array([[1.0], [0.25]]))
+    # one-hot rows: the hot index and a gap of one (noiseless posteriors)
+    agree("one-hot", np.eye(6)[[3, 0, 5]])
+    # a maximum in the last column and a runner-up equal to the next value (sorted-order traps)
+    agree("max last", np.array([[0.1, 0.2, 0.3, 0.4], [0.3, 0.3, 0.0, 0.4]]))
+    # closed forms that do not go through the scan above
+    w = np.array([[0.2, 0.5, 0.3], [0.6, 0.1, 0.3], [0.5, 0.0, 0.5]])
+    i, g = fn(w)
+    if list(np.asarray(i)) != [1, 0, 0] or not np.allclose(g, [0.2, 0.3, 0.0], atol=1e-15):
+        fails.append("closed form")
+    return fails
+
+
+def test_argmax_margin_pinned():
+    """Reading of the argmax rule: the lowest window index wins a tie, and the margin is the gap
+    between the two largest posteriors (eq. (15) gives the posteriors; a rotation whose weight is
+    not exceeded by any other is the most probable one).  The pin is a plain scan of each row plus
+    closed forms on hand-made rows."""
+    assert _argmax_margin_failures(oracle.argmax_margin) == []
+
+
+def _highest_index_wins(w):
+    w = np.asarray(w)
+    idx = w.shape[1] - 1 - np.argmax(w[:, ::-1], axis=1)
+    return idx, oracle.argmax_margin(w)[1]
+
+
+def _ratio_margin(w):
+    idx, _ = oracle.argmax_margin(w)
+    top2 = np.sort(w, axis=1)[:, -2:] if w.shape[1] > 1 else np.concatenate([w, w], axis=1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return idx, top2[:, 1] / top2[:, 0]
+
+
+def _single_rotation_zero(w):
+    idx, g = oracle.argmax_margin(w)
+    return idx, (np.zeros_like(g) if w.shape[1] == 1 else g)
+
+
+def _distinct_runner_up(w):
+    """Takes the runner-up as the largest value below the maximum (a tie would give a gap > 0)."""
+    idx = np.argmax(w, axis=1)
+    gaps = []
+    for row in w:
+        m = row.max()
+        below = row[row < m]
+        gaps.append(m - (below.max() if below.size else 0.0))
+    return idx, np.array(gaps)
+
+
+@pytest.mark.parametrize("planted", [_highest_index_wins, _ratio_margin, _single_rotation_zero,
+                                     _distinct_runner_up])
+def test_argmax_margin_pin_rejects_planted_mistakes(planted):
+    """Plausible mistakes in the argmax rule fail the pin above."""
+    assert _argmax_margin_failures(planted) != []
