@@ -57,7 +57,9 @@ typedef enum {
 typedef enum { EM_FP64 = 0, EM_FP32 = 1, EM_BF16X3 = 2, EM_FP16 = 3, EM_BF16 = 4 } em_precision;
 
 /* flags */
-#define EM_FLAG_KEEP_LSE  (1ull << 0)   /* em_step also stores the per-observation log-likelihood */
+#define EM_FLAG_KEEP_LSE  (1ull << 0)   /* em_step also stores the per-observation log-likelihood
+                                           (in the buffer the adjoint checkpoints into, so an
+                                           em_step with this flag voids the last em_loglik_fwd) */
 #define EM_FLAG_TIMING    (1ull << 1)   /* time every E+M pass with HIP events (em_pass_time)     */
 #define EM_FLAG_GENERAL_PASS (1ull << 2) /* never use the register-resident-template pass variant */
 #define EM_FLAG_WIDE_PASS (1ull << 3)   /* EM_FP16 / EM_BF16: always use the wide-row pass variant
@@ -142,7 +144,9 @@ em_status em_set_state(em_ctx *ctx, const double *a, const double *rho, int64_t 
  *  grad_a_dev   device, 2D doubles: dLL/dRe a + i dLL/dIm a, i.e. (2/sigma2) (S - N a)
  *  grad_sigma2  host: -N D / sigma2 + sum_ji w_ji ||R_i a - v_j||^2 / sigma2^2
  *  grad_eta_dev device, W doubles: W_t - N rho, or NULL
- * Returns EM_ESTATE without a preceding successful forward.  Synchronises. */
+ * Returns EM_ESTATE without a preceding successful forward, or when em_set_state or an em_step
+ * of a context made with EM_FLAG_KEEP_LSE ran after it (the checkpoint no longer matches the
+ * forward's inputs; run the forward again).  Synchronises. */
 em_status em_loglik_fwd(em_ctx *ctx, const double *a_dev, double sigma2, const double *eta_dev,
                         double *ll);
 em_status em_loglik_bwd(em_ctx *ctx, double g, double *grad_a_dev, double *grad_sigma2,

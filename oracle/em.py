@@ -97,7 +97,11 @@ def distances_brute(V, a, kbar, L, offs) -> np.ndarray:
 def distances(V, a, kbar, L, offs) -> np.ndarray:
     """Same as ``distances_brute`` via ||v||^2 + ||a||^2 - 2 Re<v_j, R_{o_i} a> and one matmul."""
     T = a[:, None] * grid_phase(kbar, offs, L, -1).T            # D x W, column i = R_{o_i} a
-    C = V.real @ T.real + V.imag @ T.imag                       # Re(conj(v_j) . t_i)
+    # Re(conj(v_j) . t_i) = Re v . Re t + Im v . Im t; the parts are copied into plain arrays
+    # so that numpy hands both products to BLAS (strided views take a slow loop)
+    Vr, Vi = np.ascontiguousarray(V.real), np.ascontiguousarray(V.imag)
+    Tr, Ti = np.ascontiguousarray(T.real), np.ascontiguousarray(T.imag)
+    C = Vr @ Tr + Vi @ Ti
     vn = np.sum(V.real ** 2 + V.imag ** 2, axis=1)
     an = float(np.sum(a.real ** 2 + a.imag ** 2))
     return vn[:, None] + an - 2.0 * C

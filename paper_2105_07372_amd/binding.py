@@ -170,6 +170,10 @@ class EM:
                          _dptr(pr) if pr is not None else None, C.c_void_p(self._stream))
         _check(st, None)
         self._ctx = ctx
+        self._keep_lse = bool(keep_lse)
+        # bumped whenever the library's adjoint checkpoint stops matching the last loglik_fwd
+        # (a new forward, an EM step that stores its own LSE, a state reset): MarginalLogLik's
+        # backward then runs its forward again
         self._fwd_gen = 0
 
     # -- lifecycle
@@ -198,6 +202,8 @@ class EM:
         """Run up to n iterations; returns (iterations done, log-likelihood of the last
         iteration's starting state) when sync, else (None, None) without waiting."""
         done, ll = C.c_int32(0), C.c_double(0.0)
+        if self._keep_lse and n > 0:
+            self._fwd_gen += 1
         if sync:
             _check(load().em_step(self._c(), int(n), float(tol), C.byref(done), C.byref(ll)),
                    self._ctx)
@@ -234,6 +240,7 @@ class EM:
     def set_state(self, a, rho=None, t: int = 0):
         av = np.ascontiguousarray(np.asarray(a, dtype=np.complex128)).view(np.float64)
         rv = None if rho is None else np.ascontiguousarray(rho, dtype=np.float64)
+        self._fwd_gen += 1
         _check(load().em_set_state(self._c(), _dptr(av), _dptr(rv) if rv is not None else None,
                                    int(t)), self._ctx)
 

@@ -679,7 +679,12 @@ em_status em_step(em_ctx *c, int32_t n_iter, double tol, int32_t *iters_done, do
     }
     const double coef = 2.0 / c->sigma2;
     int flags = PF_ACC_M | PF_CHECK_STOP;
-    if (c->flags & EM_FLAG_KEEP_LSE) flags |= PF_STORE_LSE;
+    if (c->flags & EM_FLAG_KEEP_LSE) {
+        // the per-row LSE buffer is also the adjoint's checkpoint: once an EM pass overwrites it
+        // at a_t, it no longer belongs to the last em_loglik_fwd
+        flags |= PF_STORE_LSE;
+        if (n_iter > 0) c->fwd_valid = false;
+    }
     FinArgs F = fin_base(c, FIN_EM);
     F.tol = tol;
     for (int it = 0; it < n_iter; ++it) {

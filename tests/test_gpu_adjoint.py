@@ -148,3 +148,42 @@ def test_adjoint_full_size_windowed(gpu):
     assert np.linalg.norm(ga.cpu().numpy() - ga_o) <= 1e-3 * np.linalg.norm(ga_o)
     assert abs(gs - gs_o) <= 1e-3 * abs(gs_o)
     em.close()
+
+
+@pytest.mark.parametrize("between", ["step_keep_lse", "set_state"])
+def test_checkpoint_invalidated_between_forward_and_backward(gpu, between):
+    """An EM step that stores its own per-row LSE (keep_lse) or a state reset between the forward
+    and the backward: the raw backward refuses (EM_ESTATE), and the autograd Function runs the
+    forward again, so its gradients are still those of the forward's inputs (oracle)."""
+    import torch
+    from paper_2105_07372_amd import EM, SynchemError
+    from paper_2105_07372_amd.autograd import marginal_loglik
+    w, V, lo, eta, a, s2 = _fd_problem(16)
+    rho = _rho(eta)
+    em = EM(torch.from_numpy(V).to(gpu), K=w.K, Q=w.Q, L=w.L, sigma2=s2, window=(lo, 16),
+            prior=rho, precision="fp64", keep_lse=True)
+
+    def disturb():
+        if between == "step_keep_lse":
+            em.step(2)                       # moves a_t and rewrites the LSE buffer
+        else:
+            em.set_state(V[3], rho, 0)
+
+    a_d = torch.from_numpy(a).to(gpu)
+    em.loglik_fwd(a_d, s2)
+    disturb()
+    with pytest.raises(SynchemError) as ei:
+        em.loglik_bwd(1.0, torch.empty_like(a_d))
+    assert ei.value.status == -4
+    a_t = torch.from_numpy(a).to(gpu).requires_grad_(True)
+    s_t = torch.tensor(s2, dtype=torch.float64, device=gpu, requires_grad=True)
+    e_t = torch.from_numpy(eta).to(gpu).requires_grad_(True)
+    ll = marginal_loglik(em, a_t, s_t, e_t)
+    disturb()
+    ga, gs, ge = torch.autograd.grad(ll, (a_t, s_t, e_t))
+    ll_o, ga_o, gs_o, ge_o = oracle.grad_loglik(V, a, s2, rho, w.kbar, w.L, oracle.offsets(lo, 16))
+    assert abs(ll.item() - ll_o) <= 1e-10 * abs(ll_o)
+    assert np.linalg.norm(ga.cpu().numpy() - ga_o) <= 1e-9 * np.linalg.norm(ga_o)
+    assert abs(gs.item() - gs_o) <= 1e-9 * abs(gs_o)
+    assert np.abs(ge.cpu().numpy() - ge_o).max() <= 1e-9 * max(1.0, np.abs(ge_o).max())
+    em.close()

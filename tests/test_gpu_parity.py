@@ -109,7 +109,21 @@ def test_teacher_forced_step(gpu, prec, case):
     assert er <= TOL[prec]["a"], (prec, er)
     st = em.stats()
     assert st.shape == (1, 6)
+    assert st[0, 0] == 0
     assert abs(st[0, 1] - ll_ref) <= TOL[prec]["ll"] * abs(ll_ref)
+    # MAP objective of the starting state (eq. (12) with the priors of eqs. (23)-(24)): the prior
+    # terms are exact FP64 functions of (a_t, rho_t), so it carries the log-likelihood's error
+    assert abs(st[0, 2] - it["J"]) <= TOL[prec]["ll"] * abs(ll_ref) + 1e-12 * abs(it["J"])
+    # ||a_{t+1} - a_t||^2 moves by at most ~2 ||a_{t+1} - a_t|| ||error of a_{t+1}||
+    da2 = float(np.sum(np.abs(it["a"] - a_t) ** 2))
+    err_a = TOL[prec]["a"] * np.linalg.norm(it["a"])
+    assert abs(st[0, 3] - da2) <= 3 * np.sqrt(da2) * err_a + err_a ** 2 + 1e-12 * da2
+    # entropy of rho_{t+1}: |dH| <= sum_i |log rho_i + 1| |d rho_i|
+    r1 = it["rho"]
+    nz = r1 > 0
+    ent = -float(np.sum(r1[nz] * np.log(r1[nz])))
+    bar = float(np.sum(np.abs(np.log(r1[nz]) + 1))) * TOL[prec]["a"] * 3 + 1e-12
+    assert abs(st[0, 5] - ent) <= bar, (st[0, 5], ent)
     # the stopping metric moves by at most ~2 sqrt(metric) ||delta a|| with the estimate's error
     na = np.linalg.norm(a1)
     bar = 3 * np.sqrt(it["stop"]) * TOL[prec]["a"] * na + 1e-12 * na * na
@@ -236,7 +250,7 @@ def test_nonfinite_observations_rejected(gpu):
 
 
 @pytest.mark.parametrize("prec,factored", [("bf16x3", False), ("fp16", False), ("fp32", True),
-                                           ("fp16", True)])
+                                           ("fp16", True), ("bf16x3", True)])
 def test_full_size_windowed_step(gpu, prec, factored):
     """The windowed workload at full size (N=1e5, D=512, L=360, W=49, gamma=100), with the
     correlation pass and with the factored pass: one EM step from a_0 = mean v, the estimate and

@@ -139,23 +139,19 @@ def test_large_image_adjoint(gpu):
 def test_large_image_full_size(gpu):
     """N = 10^6, D = 2048, L = 720, W = 181, fp16, in the launch configuration the library picks:
     posteriors, argmax and margins of 1024 sampled rows (first and last generator chunks) against
-    the oracle at a state set by the test; then one EM step, whose estimate and distribution must
-    equal the M-step (eq. (17)) and distribution update (eq. (18) with the prior) evaluated in FP64
-    from the kernel's own posteriors over all rows."""
+    the oracle at a state set by the test; then one EM step, whose estimate, distribution and
+    log-likelihood must equal the oracle's iteration from the same state, streamed over all rows
+    (tests/oracle_stream.py)."""
     import torch
     from paper_2105_07372_amd import EM
+    from oracle_stream import large_image_state, upload_and_iterate
     w = wl.WORKLOADS["c5"]
-    a_true = wl.image(w, 0)
-    s2 = wl.noise_variance(a_true, w.snr)
     lo, W = w.window
-    rb, _, _ = oracle.histogram_prior(wl.prior_error_draws(w, 0), w.L, lo, W)
-    obs = torch.empty((w.N, w.D), dtype=torch.complex64, device=gpu)
-    for r0, ch in wl.observation_chunks(w, 0, dtype=np.complex64, a=a_true, workers=16):
-        obs[r0:r0 + len(ch)].copy_(torch.from_numpy(ch))
-    print("large image full size: generated", flush=True)
-    rng = np.random.default_rng(11)
-    a_t = 0.9 * a_true + 0.05 * np.sqrt(s2) * (rng.standard_normal(w.D) + 1j * rng.standard_normal(w.D))
+    a_true, s2, rb, a_t = large_image_state(w, 0)
     rho_t = rb
+    obs = torch.empty((w.N, w.D), dtype=torch.complex64, device=gpu)
+    ref = upload_and_iterate(w, 0, obs, a_true, a_t, rho_t, s2, rb, w.gamma)
+    print("large image full size: generated, oracle iteration streamed", flush=True)
     em = EM(obs, K=w.K, Q=w.Q, L=w.L, sigma2=s2, window=(lo, W), prior=rb, gamma=w.gamma,
             precision="fp16", timing=True)
     assert em.info()["kernel"].startswith("pass_wide_kernel"), em.info()
@@ -165,25 +161,11 @@ def test_large_image_full_size(gpu):
         Vs = Vs.astype(np.complex128)
         _post_check(em, Vs, a_t, rho_t, s2, w, lo, W, "fp16", row0=r0)
     print("large image full size: sampled rows ok", flush=True)
-    # M-step from the kernel's posteriors, FP64
-    offs = oracle.offsets(lo, W)
-    E = torch.from_numpy(np.exp(1j * 2 * np.pi * np.outer(offs, w.kbar) / w.L)).to(gpu)
-    Z = torch.zeros((W, w.D), dtype=torch.complex128, device=gpu)
-    Wsum = torch.zeros(W, dtype=torch.float64, device=gpu)
-    step = 65536
-    for r0 in range(0, w.N, step):
-        n = min(step, w.N - r0)
-        P, _, _ = em.posterior(r0, n)
-        P64 = P.to(torch.float64)
-        Wsum += P64.sum(dim=0)
-        Z += P64.to(torch.complex128).t().contiguous() @ obs[r0:r0 + n].to(torch.complex128)
-    a_ref = ((E * Z).sum(dim=0) / w.N).cpu().numpy()
-    wt = Wsum.cpu().numpy() + w.gamma * rb
-    rho_ref = wt / wt.sum()
     em.step(1)
     a1, rho1, _ = em.state()
-    assert np.linalg.norm(a1 - a_ref) / np.linalg.norm(a_ref) <= 1e-5
-    assert np.abs(rho1 - rho_ref).max() <= 1e-6
+    assert np.linalg.norm(a1 - ref["a"]) / np.linalg.norm(ref["a"]) <= 2e-4
+    assert np.abs(rho1 - ref["rho"]).max() <= 2e-4 * ref["rho"].max()
+    assert abs(em.stats()[-1, 1] - ref["ll"]) <= 1e-6 * abs(ref["ll"])
     em.pass_time(reset=True)
     em.step(3)
     ms, n = em.pass_time(reset=True)
