@@ -220,6 +220,19 @@ em_status em_align(const void *obs_dev, int64_t N, int32_t K, int32_t Q, const d
 em_status em_aligned_mean(const void *obs_dev, int64_t N, int32_t K, int32_t Q,
                           const double *theta_dev, double *mean_dev, void *stream);
 
+/* em_aligned_mean for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same arguments, the same kernels and
+ * the same result bit for bit, but no hipMalloc, hipFree or allocating library call.  Its
+ * partial sums live in the library's own static device array of 8 MiB per GPU (256 x 2 x 2048
+ * doubles, held until the process ends), which covers every D the library accepts (D <= 2048;
+ * larger shapes are rejected with EM_EUNSUPPORTED before any device work).  The work is enqueued
+ * on `stream` and the call returns without waiting: mean_dev is ready in stream order.  All calls
+ * on one GPU share that array, so calls that overlap on one GPU (on different streams, or from
+ * several threads) race and must be serialised by the caller.  Errors as em_aligned_mean
+ * (em_last_error(NULL)); a failure to look up the array's address returns EM_EDEVICE. */
+em_status em_aligned_mean_noalloc(const void *obs_dev, int64_t N, int32_t K, int32_t Q,
+                                  const double *theta_dev, double *mean_dev, void *stream);
+
 /* Binned centred errors of a synchronizer (§III-B, Algorithm "learning rotation distribution"):
  * bins_dev[i] = floor((theta_hat_i - theta_i - 2 pi lc / L) L / (2 pi)) mod L (FP64), for
  * em_learn_prior.  theta_hat_dev, theta_dev: N doubles (radians); lc: the centring rotation on

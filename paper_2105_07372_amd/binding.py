@@ -75,6 +75,7 @@ def load() -> C.CDLL:
         "em_sync_match": (i32, [vp, i64, i32, i32, i32, i64, i32, vp, vp, vp]),
         "em_align": (i32, [vp, i64, i32, i32, vp, vp, vp]),
         "em_aligned_mean": (i32, [vp, i64, i32, i32, vp, vp, vp]),
+        "em_aligned_mean_noalloc": (i32, [vp, i64, i32, i32, vp, vp, vp]),
         "em_error_bins": (i32, [vp, vp, i64, i32, i32, vp, vp]),
         "em_set_stream": (i32, [vp, vp]),
         "em_pass_time": (i32, [vp, P(dbl), P(i64), i32]),
@@ -389,16 +390,23 @@ def align(obs, K: int, Q: int, theta, stream=None):
     return out
 
 
-def aligned_mean(obs, K: int, Q: int, theta, stream=None):
-    """(1/N) sum_i v_i o exp(+i kbar theta_i) as a complex128 CUDA tensor (em_aligned_mean)."""
+def aligned_mean(obs, K: int, Q: int, theta, stream=None, out=None, noalloc: bool = False):
+    """(1/N) sum_i v_i o exp(+i kbar theta_i) as a complex128 CUDA tensor (em_aligned_mean).
+    noalloc=True calls em_aligned_mean_noalloc (the library allocates nothing; the result is
+    ready in stream order); out, if given, is a contiguous CUDA complex128 tensor of K*Q."""
     import torch
     if not (theta.is_cuda and theta.dtype == torch.float64 and theta.is_contiguous()
             and theta.numel() == obs.shape[0]):
         raise ValueError("theta must be a contiguous CUDA float64 tensor with one entry per row")
-    out = torch.empty(K * Q, dtype=torch.complex128, device=obs.device)
-    st = load().em_aligned_mean(_obs_c64(obs, K, Q), int(obs.shape[0]), int(K), int(Q),
-                                C.c_void_p(theta.data_ptr()), C.c_void_p(out.data_ptr()),
-                                C.c_void_p(_stream_handle(stream)))
+    if out is None:
+        out = torch.empty(K * Q, dtype=torch.complex128, device=obs.device)
+    elif not (out.is_cuda and out.dtype == torch.complex128 and out.is_contiguous()
+              and out.numel() == K * Q):
+        raise ValueError("out must be a contiguous CUDA complex128 tensor of K*Q entries")
+    fn = load().em_aligned_mean_noalloc if noalloc else load().em_aligned_mean
+    st = fn(_obs_c64(obs, K, Q), int(obs.shape[0]), int(K), int(Q),
+            C.c_void_p(theta.data_ptr()), C.c_void_p(out.data_ptr()),
+            C.c_void_p(_stream_handle(stream)))
     _check(st, None)
     return out
 

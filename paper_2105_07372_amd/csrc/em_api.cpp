@@ -1038,7 +1038,7 @@ em_status em_aligned_mean(const void *obs_dev, int64_t N, int32_t K, int32_t Q,
         return fail(nullptr, EM_EINVAL, "obs_dev, theta_dev and mean_dev are required");
     hipStream_t s = (hipStream_t)stream;
     const int D = K * Q;
-    const int G = (int)std::min<int64_t>(N, 1024);
+    const int G = (int)std::min<int64_t>(N, kAlignedMeanBlocks);
     DevBufs buf;
     double *part = nullptr, *sum = nullptr;
     if (!buf.get((void **)&part, (size_t)G * 2 * D * sizeof(double)) ||
@@ -1048,6 +1048,30 @@ em_status em_aligned_mean(const void *obs_dev, int64_t N, int32_t K, int32_t Q,
     if (e == hipSuccess) e = launch_reduce(part, G, 2 * D, sum, s);
     if (e == hipSuccess) e = launch_scale(sum, mean_dev, 2 * D, 1.0 / (double)N, s);
     e = finish(e, s);
+    return hip_status(e, "aligned mean");
+}
+
+em_status em_aligned_mean_noalloc(const void *obs_dev, int64_t N, int32_t K, int32_t Q,
+                                  const double *theta_dev, double *mean_dev, void *stream) {
+    g_err.clear();
+    em_status st = sync_shape(N, K, Q);          // D <= kMaxD: the partials fit the scratch
+    if (st != EM_OK) return st;
+    if (!obs_dev || !theta_dev || !mean_dev)
+        return fail(nullptr, EM_EINVAL, "obs_dev, theta_dev and mean_dev are required");
+    const int D = K * Q;
+    const int G = (int)std::min<int64_t>(N, kAlignedMeanBlocks);
+    double *part = nullptr;
+    size_t cap = 0;
+    hipError_t e = noalloc_scratch(&part, &cap);
+    if (e != hipSuccess) return hip_status(e, "scratch address");
+    if ((size_t)G * 2 * D * sizeof(double) > cap)
+        return fail(nullptr, EM_EUNSUPPORTED, "partial sums exceed the library's scratch");
+    hipStream_t s = (hipStream_t)stream;
+    // every partial is written by the column-sum kernel before the reduction reads it; the sum
+    // goes straight into mean_dev and is scaled there (the same operations as em_aligned_mean)
+    e = launch_aligned_colsum((const float2 *)obs_dev, N, K, Q, theta_dev, part, G, s);
+    if (e == hipSuccess) e = launch_reduce(part, G, 2 * D, mean_dev, s);
+    if (e == hipSuccess) e = launch_scale(mean_dev, mean_dev, 2 * D, 1.0 / (double)N, s);
     return hip_status(e, "aligned mean");
 }
 

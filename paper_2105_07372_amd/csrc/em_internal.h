@@ -134,6 +134,13 @@ hipError_t launch_aligned_colsum(const float2 *V, int64_t N, int K, int Q, const
                                 double *partials, int G, hipStream_t s);
 hipError_t launch_error_bins(const double *theta_hat, const double *theta, int64_t N, int L,
                              int lc, int *bins, hipStream_t s);
+// Workgroups of the aligned column sums (both aligned-mean entry points use this many, so their
+// fixed-order sums are the same).
+constexpr int kAlignedMeanBlocks = 256;
+// The library's own device scratch for em_aligned_mean_noalloc (sync_kernels.hip): the current
+// device's address of a static array of kAlignedMeanBlocks x 2 kMaxD doubles, looked up once per
+// device (*bytes receives its size).
+hipError_t noalloc_scratch(double **ptr, size_t *bytes);
 hipError_t launch_softmax(const double *eta, double *rho, float *logrho32, double *logrho64,
                           int W, int Wp, hipStream_t s);
 hipError_t launch_logrho(const double *rho, float *logrho32, double *logrho64, int W, int Wp,

@@ -18,6 +18,8 @@
 
 #include <math.h>
 
+#include <mutex>
+
 namespace sem {
 
 typedef float f32x4s __attribute__((ext_vector_type(4)));
@@ -592,6 +594,37 @@ hipError_t launch_aligned_colsum(const float2 *V, int64_t N, int K, int Q, const
     hipLaunchKernelGGL(aligned_colsum_kernel, dim3(G), dim3(256), 0, s, V, N, K, Q, theta,
                        partials);
     return hipGetLastError();
+}
+
+// Scratch of the aligned-mean entry point that allocates nothing: the per-workgroup partial
+// column sums, kAlignedMeanBlocks x 2 kMaxD doubles (8 MiB), one copy per device for the life of
+// the process.  Host code never passes the array's name to a kernel (on the host it is only a
+// stand-in for the symbol); it passes the device address that hipGetSymbolAddress returns for
+// the current device, looked up once per device and kept.
+static __device__ __align__(256) double scratch[(size_t)kAlignedMeanBlocks * 2 * kMaxD];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(double **ptr, size_t *bytes) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    *bytes = sizeof(scratch);
+    return hipSuccess;
 }
 
 hipError_t launch_error_bins(const double *theta_hat, const double *theta, int64_t N, int L,

@@ -123,6 +123,12 @@ def test_sync_calls_validate_before_device_work(lib):
     assert lib.em_sync_match(ok, 100, 4, 4, 5000, 10, 5, ok, None, None) == B.EM_EINVAL
     assert lib.em_align(ok, 0, 4, 4, ok, ok, None) == B.EM_EINVAL
     assert lib.em_align(ok, 10, 4, 4, None, ok, None) == B.EM_EINVAL
+    for fn in (lib.em_aligned_mean, lib.em_aligned_mean_noalloc):
+        assert fn(ok, 0, 4, 4, ok, ok, None) == B.EM_EINVAL
+        assert fn(ok, 10, 4, 4, None, ok, None) == B.EM_EINVAL
+        assert fn(ok, 10, 4, 4, ok, None, None) == B.EM_EINVAL
+        assert fn(ok, 10, 64, 64, ok, ok, None) == B.EM_EUNSUPPORTED    # D above the scratch
+        assert "2048" in lib.em_last_error(None).decode()
     assert st[B.EM_EINVAL]
 
 
