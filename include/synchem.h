@@ -61,7 +61,10 @@ typedef enum { EM_FP64 = 0, EM_FP32 = 1, EM_BF16X3 = 2, EM_FP16 = 3, EM_BF16 = 4
                                            (in the buffer the adjoint checkpoints into, so an
                                            em_step with this flag voids the last em_loglik_fwd) */
 #define EM_FLAG_TIMING    (1ull << 1)   /* time every E+M pass with HIP events (em_pass_time)     */
-#define EM_FLAG_GENERAL_PASS (1ull << 2) /* never use the register-resident-template pass variant */
+#define EM_FLAG_GENERAL_PASS (1ull << 2) /* use the general pass (template streamed from L2, row
+                                           tiles in LDS) instead of the specialised correlation
+                                           passes (register-resident template; the FP32 GEMM with
+                                           its posterior / M-step epilogue) */
 #define EM_FLAG_WIDE_PASS (1ull << 3)   /* EM_FP16 / EM_BF16: always use the wide-row pass variant
                                            (chosen by itself when a row tile does not fit in LDS) */
 #define EM_FLAG_FACTORED  (1ull << 4)   /* evaluate the correlations through the per-frequency sums
@@ -70,6 +73,9 @@ typedef enum { EM_FP64 = 0, EM_FP32 = 1, EM_BF16X3 = 2, EM_FP16 = 3, EM_BF16 = 4
                                            of-two multiple of 8 (any precision but EM_FP64), or
                                            D = 2048 in EM_FP16 / EM_BF16 with Q a power-of-two
                                            multiple of 16; else EM_EUNSUPPORTED */
+#define EM_FLAG_STAGED_PASS (1ull << 5) /* EM_FP16 / EM_BF16 with D = 512: use the pass that stages
+                                           whole row tiles in LDS instead of the row-stream pass
+                                           (both are the correlation GEMM; for comparisons) */
 
 typedef struct {
     int64_t n_obs;          /* N >= 1                                                        */

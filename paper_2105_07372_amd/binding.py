@@ -20,6 +20,7 @@ STATUS_NAMES = {0: "EM_OK", -1: "EM_EINVAL", -2: "EM_ENOMEM", -3: "EM_EDEVICE",
                 -4: "EM_ESTATE", -5: "EM_ENONFINITE", -6: "EM_EUNSUPPORTED"}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp16": 3, "bf16": 4}
 EM_FLAG_KEEP_LSE, EM_FLAG_TIMING, EM_FLAG_GENERAL_PASS, EM_FLAG_WIDE_PASS = 1, 2, 4, 8
+EM_FLAG_STAGED_PASS = 32
 EM_FLAG_FACTORED = 16
 EM_STATS_FIELDS = 6
 STATS_COLUMNS = ("t", "loglik", "objective", "delta_a2", "stop_metric", "entropy_rho")
@@ -123,7 +124,7 @@ class EM:
                  update_rho: bool = True, precision: str = "fp32", gamma_a_inv=None, a0=None,
                  keep_lse: bool = False, timing: bool = False, general_pass: bool = False,
                  wide_pass: bool = False, factored: bool = False, angles=None,
-                 stream=None):
+                 staged_pass: bool = False, stream=None):
         import torch
         lib = load()
         if precision not in PRECISIONS:
@@ -149,7 +150,8 @@ class EM:
         p.flags = ((EM_FLAG_KEEP_LSE if keep_lse else 0) | (EM_FLAG_TIMING if timing else 0)
                    | (EM_FLAG_GENERAL_PASS if general_pass else 0)
                    | (EM_FLAG_WIDE_PASS if wide_pass else 0)
-                   | (EM_FLAG_FACTORED if factored else 0))
+                   | (EM_FLAG_FACTORED if factored else 0)
+                   | (EM_FLAG_STAGED_PASS if staged_pass else 0))
         keep = []
         if gamma_a_inv is not None:
             g = np.ascontiguousarray(gamma_a_inv, dtype=np.float64)

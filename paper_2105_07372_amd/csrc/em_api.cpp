@@ -43,6 +43,10 @@ struct em_ctx {
     bool wide = false;    // wide-row pass (rows streamed through an LDS ring, 128-row tiles)
     int wNTW = 0, wUR = 0;
     bool fac = false;     // factored pass (per-frequency sums; no template)
+    bool kr = false;      // row-stream correlation pass (template in registers, rows via LDS)
+    int krNT = 0;
+    bool gm = false;      // long-window FP32 pass (GEMM with a posterior / M-step epilogue)
+    int gmNT = 0;
     int fWIDE = 0, fKCM = 0, fEPL = 8;
     bool has_angles = false;   // the window is an explicit angle list (em_params.angles)
     int64_t rowbytes = 0;
@@ -150,6 +154,8 @@ em_status plan(em_ctx *c, size_t lds_max) {
     c->ks = false;
     c->wide = false;
     c->fac = false;
+    c->kr = false;
+    c->gm = false;
     if (c->flags & EM_FLAG_FACTORED) {
         int WIDE = 0, KCM = 0, EPL = 8, BM = 0;
         size_t lds = 0;
@@ -183,6 +189,30 @@ em_status plan(em_ctx *c, size_t lds_max) {
             return EM_OK;
         }
         return fail(c, EM_EUNSUPPORTED, "no wide-row pass variant for this window and K");
+    }
+    if (c->prec == P_F32 && !(c->flags & EM_FLAG_GENERAL_PASS)) {
+        int NT = 0;
+        size_t lds = 0;
+        if (gm_plan(c->prec, c->D, c->K, c->Q, c->Wp, lds_max, &NT, &lds)) {
+            c->gm = true;
+            c->BM = 128;
+            c->gmNT = NT;
+            c->WM = 0;
+            c->lds = lds;
+            return EM_OK;
+        }
+    }
+    if (one_plane && !(c->flags & (EM_FLAG_GENERAL_PASS | EM_FLAG_STAGED_PASS))) {
+        int NT = 0;
+        size_t lds = 0;
+        if (kr_plan(c->prec, c->D, c->Dp, c->Q, c->Wp, lds_max, &NT, &lds)) {
+            c->kr = true;
+            c->BM = 16;
+            c->krNT = NT;
+            c->WM = 0;
+            c->lds = lds;
+            return EM_OK;
+        }
     }
     if (c->prec != P_F64 && c->prec != P_F32 && !(c->flags & EM_FLAG_GENERAL_PASS)) {
         int BM = 0, NT = 0, KSS = 0;
@@ -264,7 +294,7 @@ em_status check_params(const em_params *p) {
     if (p->precision < EM_FP64 || p->precision > EM_BF16)
         return fail(nullptr, EM_EINVAL, "unknown precision");
     if (p->flags & ~(uint64_t)(EM_FLAG_KEEP_LSE | EM_FLAG_TIMING | EM_FLAG_GENERAL_PASS |
-                               EM_FLAG_WIDE_PASS | EM_FLAG_FACTORED))
+                               EM_FLAG_WIDE_PASS | EM_FLAG_FACTORED | EM_FLAG_STAGED_PASS))
         return fail(nullptr, EM_EINVAL, "unknown flag bits");
     if (p->window_lo < -(1 << 30) || p->window_lo > (1 << 30))
         return fail(nullptr, EM_EINVAL, "window_lo out of range");
@@ -351,7 +381,11 @@ em_status run_pass(em_ctx *c, int flags, int64_t r0, int64_t r1, const double *a
     if (grid < 1) grid = 1;
     const bool ev = timed && c->timing && c->ev_used + 2 <= 2 * kTimingEvents;
     if (ev) HIPCHK(c, hipEventRecord(c->ev[c->ev_used], c->stream));
-    if (c->ks)
+    if (c->kr)
+        HIPCHK(c, launch_pass_kr(c->prec, c->krNT, A, grid, c->lds, c->stream));
+    else if (c->gm)
+        HIPCHK(c, launch_pass_gm(c->gmNT, A, grid, c->lds, c->stream));
+    else if (c->ks)
         HIPCHK(c, launch_pass_ks(c->prec, c->BM, c->ksNT, c->ksKSS, A, grid, c->lds, c->stream));
     else if (c->wide)
         HIPCHK(c, launch_pass_wide(c->prec, c->wNTW, c->wUR, A, grid, c->lds, c->stream));
@@ -498,7 +532,17 @@ em_status em_init(em_ctx **out, const em_params *p, const void *obs_dev, const d
     }
     if ((st = plan(c, (size_t)ldsmax)) != EM_OK) return bail(st);
     int occ = 1;
-    if (c->ks) {
+    if (c->gm) {
+        if (pass_gm_setup(c->gmNT, c->lds, &occ) != hipSuccess || occ < 1) {
+            (void)hipGetLastError();
+            occ = 1;
+        }
+    } else if (c->kr) {
+        if (pass_kr_setup(c->prec, c->krNT, c->lds, &occ) != hipSuccess || occ < 1) {
+            (void)hipGetLastError();
+            occ = 1;
+        }
+    } else if (c->ks) {
         if (pass_ks_setup(c->prec, c->BM, c->ksNT, c->ksKSS, c->lds, &occ) != hipSuccess ||
             occ < 1) {
             (void)hipGetLastError();
@@ -692,7 +736,7 @@ em_status em_step(em_ctx *c, int32_t n_iter, double tol, int32_t *iters_done, do
                                 c->logrho64, coef, nullptr, nullptr, nullptr, true, true);
         if (st != EM_OK) return st;
         HIPCHK(c, launch_reduce_finalize(F, c->partials, c->grid, c->ncols, c->red, c->stream));
-        if (!c->ks && !c->fac)   // these passes use a_t itself
+        if (!c->ks && !c->fac && !c->kr)   // these passes use a_t itself
             if ((st = run_template(c, c->a, c->Thi, c->Tlo, c->tscale, true)) != EM_OK) return st;
     }
     if (iters_done || ll_last) {
@@ -1124,7 +1168,9 @@ em_status em_get_info(const em_ctx *c, em_info *info) {
     info->bytes_per_row = c->rowbytes;
     info->lds_bytes = (int64_t)c->lds;
     std::snprintf(info->kernel, sizeof info->kernel, "%s",
-                  c->ks     ? pass_ks_name(c->prec, c->BM, c->ksNT, c->ksKSS)
+                  c->kr     ? pass_kr_name(c->prec, c->krNT)
+                  : c->gm   ? pass_gm_name(c->gmNT)
+                  : c->ks   ? pass_ks_name(c->prec, c->BM, c->ksNT, c->ksKSS)
                   : c->wide ? pass_wide_name(c->prec, c->wNTW, c->wUR)
                   : c->fac  ? pass_fac_name(c->prec, c->fWIDE, c->fKCM, c->fEPL)
                             : pass_kernel_name(c->prec, c->BM, c->WM, c->LD));

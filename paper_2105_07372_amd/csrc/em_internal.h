@@ -157,6 +157,18 @@ hipError_t launch_pass_ks(int prec, int BM, int NT, int KSS, const PassArgs &a, 
                           size_t lds, hipStream_t s);
 hipError_t pass_ks_setup(int prec, int BM, int NT, int KSS, size_t lds, int *blocks_per_cu);
 const char *pass_ks_name(int prec, int BM, int NT, int KSS);
+// Row-stream correlation pass (one 16-bit plane, D = 512, Q in {8, 16, 32, 64}, Wp <= 64).
+bool kr_plan(int prec, int D, int Dp, int Q, int Wp, size_t lds_max, int *NT, size_t *lds);
+hipError_t launch_pass_kr(int prec, int NT, const PassArgs &a, int grid, size_t lds,
+                          hipStream_t s);
+hipError_t pass_kr_setup(int prec, int NT, size_t lds, int *blocks_per_cu);
+const char *pass_kr_name(int prec, int NT);
+// Long-window FP32 pass built as a GEMM with the posterior and M-step as epilogue (D <= 512,
+// Q % 8 == 0, K <= 32, Wp <= 384).
+bool gm_plan(int prec, int D, int K, int Q, int Wp, size_t lds_max, int *NTC, size_t *lds);
+hipError_t launch_pass_gm(int NTC, const PassArgs &a, int grid, size_t lds, hipStream_t s);
+hipError_t pass_gm_setup(int NTC, size_t lds, int *blocks_per_cu);
+const char *pass_gm_name(int NTC);
 bool wide_plan(int prec, int Wp, int K, size_t lds_max, int *NTW, int *UR);
 size_t wide_lds_bytes(int K, int Wp, int NTW, int UR);
 hipError_t launch_pass_wide(int prec, int NTW, int UR, const PassArgs &a, int grid, size_t lds,

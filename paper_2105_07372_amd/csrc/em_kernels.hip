@@ -985,23 +985,42 @@ __device__ __forceinline__ void write_partials(const PassArgs &A, PassAcc<DPT> &
     }
 }
 
+// Global-to-LDS copy of BYTES (16 or 4) per lane: lane l's bytes land at lds_dst + BYTES l (lds_dst
+// wave-uniform).  Written as inline assembly so that the compiler does not make every later LDS
+// access wait for it (it cannot tell which LDS bytes such a copy writes, so with the builtin it
+// waits for all vector-memory operations before reading any LDS); its completion is tracked with
+// explicit vector-memory counts and a barrier before the bytes are read.  M0 is restored.
+template <int BYTES>
+__device__ __forceinline__ void dma_to_lds(const void *src, void *lds_dst) {
+    static_assert(BYTES == 16 || BYTES == 4, "dword or dwordx4 copies");
+    // (uniform by construction; read from the first lane so that it sits in a scalar register)
+    const uint32_t m = __builtin_amdgcn_readfirstlane(
+        (uint32_t)(uintptr_t)(__attribute__((address_space(3))) void *)lds_dst);
+    uint32_t save;
+    if constexpr (BYTES == 16)
+        asm volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\ts_nop 0\n\t"
+                     "global_load_lds_dwordx4 %1, off\n\ts_mov_b32 m0, %0"
+                     : "=&s"(save) : "v"(src), "s"(m) : "memory");
+    else
+        asm volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\ts_nop 0\n\t"
+                     "global_load_lds_dword %1, off\n\ts_mov_b32 m0, %0"
+                     : "=&s"(save) : "v"(src), "s"(m) : "memory");
+}
+
 // Asynchronous copy of one row tile into an LDS tile buffer with the direct global-to-LDS load
 // (16 bytes per lane; a wave's 64 lanes fill 1 KB of LDS in lane order).  Rows are whole 1 KB
 // chunks (rowbytes is a multiple of 1024 here); wave w copies chunks w, w + 8, ...  Completion
 // is awaited with s_waitcnt before the barrier that precedes the first read of the buffer.
 __device__ __forceinline__ void dma_issue_tile(const PassArgs &A, int64_t tile, int BM,
                                               uint8_t *buf, int RS) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t r0 = A.row_begin + tile * BM;
     const int rows = (int)((A.row_end - r0) < BM ? (A.row_end - r0) : BM);
     const int cpr = (int)(A.rowbytes >> 10);
     const int nch = rows * cpr;
     for (int c = wave; c < nch; c += kThreads / 64) {
         const int r = c / cpr, k = c - r * cpr;
-        const uint8_t *src = A.V + (r0 + r) * A.rowbytes + k * 1024 + lane * 16;
-        __builtin_amdgcn_global_load_lds(
-            (const void *)src, (__attribute__((address_space(3))) void *)(buf + r * RS + k * 1024),
-            16, 0, 0);
+        dma_to_lds<16>(A.V + (r0 + r) * A.rowbytes + k * 1024 + lane * 16, buf + r * RS + k * 1024);
     }
 }
 
@@ -1887,6 +1906,776 @@ __global__ __launch_bounds__(kThreads) void pass_wide_kernel(PassArgs A) {
 }
 
 // ------------------------------------------------------------------------------------------
+// Row-stream correlation pass (the contraction against the W rotated templates, as the method
+// states it) for one 16-bit plane of observations with D = 512 and windows up to 64, built so
+// that its row tiles stream at HBM rate: one workgroup per CU, 16-row tiles copied global-to-LDS
+// two tiles ahead of their use (three LDS buffers, completion tracked by exact vector-memory
+// counts), and two workgroup barriers per tile.
+//   * K-split: wave w owns k-steps 4w .. 4w + 3 (reals 128 w .. 128 w + 127) and holds the
+//     template rows of its slice for every window tile in registers (hi + lo, built once per
+//     launch from a_t); per tile it reads its slice of the 16 rows from LDS once (MFMA A
+//     fragments) and keeps it in registers for the M-step.
+//   * The eight partial correlations go to LDS; wave w then sums them in wave order for rows w
+//     and w + 8 (one window column per lane), forms the prior-weighted log-sum-exp and the
+//     posteriors with wave reductions, and writes the posteriors as 16-bit hi + lo planes.
+//   * U = w E is formed transposed and per wave, for the angular frequencies of the wave's own
+//     entries only (U^T = E'^T w^T: three 16x16x32 products, E' hi + lo in registers), and left
+//     in a wave-private LDS block; the M-step then runs on the wave's own row fragments, so no
+//     row is read from LDS twice and no U is shared between waves.  Per-lane FP32 sums over the
+//     lane's rows are folded into FP64 every kKrFlush tiles (16-lane DPP sums, then each lane
+//     keeps two of its group's 32 values).
+// Needs Dp = 1024 (D = 512 with Q in {8, 16, 32, 64}: a lane's four entries of a k-step share
+// one frequency and a wave's entries span at most eight) and Wp = 16 NT <= 64.
+
+constexpr int kKrBM = 16;                 // rows per tile
+constexpr int kKrBufs = 3;                // LDS row-tile buffers (two tiles in flight)
+constexpr int kKrFlush = 16;              // tiles between FP32 -> FP64 folds of the M-step sums
+constexpr int kKrWS = 144;                // bytes per posterior row of one 16-bit plane (64 + pad)
+constexpr int kKrUS = 20;                 // floats per row of a wave's U block (16 + pad)
+// Partial-correlation slots (16 B each) per (wave, window tile): lane 16 g + j's slot is 17 g + j,
+// so that both the MFMA-order writes and the row-order reads are free of bank conflicts.
+constexpr int kKrRedTile = 68;
+
+struct KrLds {
+    int RS, off_red, off_w, off_up, off_rs, off_lr, off_wacc, total;
+};
+__host__ __device__ inline KrLds kr_lds(int Dp) {
+    KrLds l;
+    l.RS = 2 * Dp + 16;                                   // staged row, padded
+    l.off_red = align_up(kKrBufs * kKrBM * l.RS, 16);     // 8 waves x 4 tiles x 64 lanes x 16 B
+    l.off_w = l.off_red + 8 * 4 * kKrRedTile * 16;
+    l.off_up = l.off_w + 2 * kKrBM * kKrWS;               // hi plane, then lo plane
+    l.off_rs = l.off_up + 8 * 16 * kKrUS * 4;             // per-wave U blocks
+    l.off_lr = l.off_rs + kKrBufs * 64 * 4;               // row scales of the buffered tiles
+    l.off_wacc = l.off_lr + 64 * 4;                       // FP64 W_t sums: 16 row lanes x 64
+    l.total = l.off_wacc + 16 * 64 * 8;
+    return l;
+}
+
+template <int P, int NT, int QRY>
+__global__ __launch_bounds__(kThreads) void pass_kr_kernel(PassArgs A) {
+    static_assert(P == P_F16 || P == P_BF16, "one 16-bit plane");
+    static_assert(NT >= 1 && NT <= 4, "windows up to 64");
+    typedef typename std::conditional<P == P_F16, _Float16, __bf16>::type H;
+    typedef typename std::conditional<P == P_F16, f16x8, bf16x8>::type H8;
+    constexpr int KSS = 4, BM = kKrBM;
+    constexpr bool query = QRY != 0;
+    if ((A.flags & PF_CHECK_STOP) && *A.stopped) return;
+
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int g = lane >> 4, rl = lane & 15;
+    const KrLds LY = kr_lds(A.Dp);
+    f32x4 *red = (f32x4 *)(smem + LY.off_red);
+    uint8_t *wsh = smem + LY.off_w;
+    float *up = (float *)(smem + LY.off_up) + wave * 16 * kKrUS;
+    float *rsb = (float *)(smem + LY.off_rs);
+    float *lrs = (float *)(smem + LY.off_lr);
+    const int D = A.D, K = A.K, Q = A.Q, W = A.W, Wp = A.Wp;
+    const bool accm = (A.flags & PF_ACC_M) != 0;
+    // exact vector-memory counts hold only while the loop issues nothing but its tile copies
+    const bool deep = !(A.flags & (PF_STORE_LSE | PF_LOAD_LSE | PF_QUERY));
+
+    for (int i = tid; i < 64; i += kThreads) lrs[i] = i < Wp ? A.logrho32[i] : -INFINITY;
+    // template scale from max |Re a|, |Im a| (a power of two, as in the other 16-bit passes)
+    double amax = 0.0;
+    for (int r = tid; r < 2 * D; r += kThreads) amax = fmax(amax, fabs(A.a[r]));
+    amax = -block_min_d(-amax, (double *)red, kThreads);
+    float sc = 1.0f, tsc = 1.0f;
+    if (amax > 0.0) {
+        const int e = ilogb(amax);
+        sc = ldexpf(1.0f, scale_target(P) - e);
+        tsc = ldexpf(1.0f, e - scale_target(P));
+    }
+    // this wave's template slice: T[r][i] = (Re, Im)(a_d exp(-i k_d theta_i)) sc, d = r / 2,
+    // B fragments (column i = 16 nt + lane % 16, reals 8 g .. 8 g + 7 of the k-step), hi + lo
+    u32x4 treg[KSS][NT][2];
+#pragma unroll
+    for (int ks = 0; ks < KSS; ++ks) {
+        const int d0 = ((wave * KSS + ks) * 32 + 8 * g) >> 1;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const float *Ei = A.E2 + (int64_t)(nt * 16 + rl) * 2 * K;
+            H hv[8], lv[8];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int d = d0 + e;
+                float tre = 0.f, tim = 0.f;
+                if (d < D) {
+                    const int k = d / Q;
+                    const float are = (float)A.a[2 * d], aim = (float)A.a[2 * d + 1];
+                    const float er = Ei[k], ei = Ei[K + k];
+                    tre = (are * er + aim * ei) * sc;
+                    tim = (aim * er - are * ei) * sc;
+                }
+                hv[2 * e] = (H)tre;
+                hv[2 * e + 1] = (H)tim;
+                lv[2 * e] = (H)(tre - (float)hv[2 * e]);
+                lv[2 * e + 1] = (H)(tim - (float)hv[2 * e + 1]);
+            }
+            treg[ks][nt][0] = __builtin_bit_cast(u32x4, hv);
+            treg[ks][nt][1] = __builtin_bit_cast(u32x4, lv);
+        }
+    }
+    // A fragments of U^T = E'^T w^T: row m of E'^T is Re (m even) or Im (m odd) of
+    // exp(+i k theta_i) at k = kbase + m / 2, the frequencies of this wave's entries
+    const int kbase = (64 * wave) / Q, nk = 64 / Q;
+    H8 eh[2], el[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        H hv[8], lv[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int i = 32 * s + 8 * g + t, k = kbase + (rl >> 1);
+            const float x = (i < Wp && (rl >> 1) < nk && k < K)
+                                ? A.E2[(int64_t)i * 2 * K + ((rl & 1) ? K : 0) + k] : 0.f;
+            hv[t] = (H)x;
+            lv[t] = (H)(x - (float)hv[t]);
+        }
+        eh[s] = __builtin_bit_cast(H8, hv);
+        el[s] = __builtin_bit_cast(H8, lv);
+    }
+    // the U column (2 (k - kbase)) each of this lane's k-steps needs
+    int um[KSS];
+#pragma unroll
+    for (int ks = 0; ks < KSS; ++ks) um[ks] = 2 * ((16 * (wave * KSS + ks) + 4 * g) / Q - kbase);
+
+    const int64_t ntiles = (A.row_end - A.row_begin + BM - 1) / BM;
+    const int64_t nmine = ntiles > (int64_t)blockIdx.x
+                              ? (ntiles - 1 - (int64_t)blockIdx.x) / gridDim.x + 1 : 0;
+    // copy of this workgroup's j-th tile into buffer b: 32 chunks of 1 KiB (wave w: chunks w,
+    // w + 8, w + 16, w + 24, i.e. rows w / 2 + 4 cc, half w % 2; rows past the end repeat the last
+    // row, so every tile issues the same number of copies), and wave 0 the 64 row scales at and
+    // after the tile's first row
+    const int64_t tstride = (int64_t)gridDim.x * BM;
+    auto issue = [&](int64_t j, int b) {
+        const int64_t r0 = A.row_begin + (int64_t)blockIdx.x * BM + j * tstride;
+        uint8_t *buf = smem + b * BM * LY.RS;
+        const int rc = wave >> 1, kc = wave & 1;
+        if (r0 + BM <= A.row_end) {
+            const uint8_t *src = A.V + (r0 + rc) * A.rowbytes + kc * 1024 + lane * 16;
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc)
+                dma_to_lds<16>(src + (int64_t)(4 * cc) * A.rowbytes,
+                               buf + (rc + 4 * cc) * LY.RS + kc * 1024);
+        } else {
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) {
+                const int r = rc + 4 * cc;
+                const int64_t row = r0 + r < A.row_end ? r0 + r : A.row_end - 1;
+                dma_to_lds<16>(A.V + row * A.rowbytes + kc * 1024 + lane * 16,
+                               buf + r * LY.RS + kc * 1024);
+            }
+        }
+        if (wave == 0) {
+            const int64_t row = r0 + lane < A.row_end ? r0 + lane : A.row_end - 1;
+            dma_to_lds<4>(A.rowscale + row, rsb + b * 64);
+        }
+    };
+
+    // posterior waves: this lane's four window columns 4 px .. 4 px + 3 (the partial slots of
+    // window tile pnt, lane group pg); the row factor; W_t of the four columns (FP32 over 16
+    // tiles, then added into FP64 sums in LDS that only this thread touches)
+    const int px = lane & 15, pnt = px >> 2, pg = px & 3;
+    const float ct = (float)A.coef * tsc;
+    float accW[4] = {0.f, 0.f, 0.f, 0.f};
+    double *wacc = (double *)(smem + LY.off_wacc) + (4 * wave + (lane >> 4)) * 64 + 4 * px;
+    if (wave < 4)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) wacc[q] = 0.0;
+    int nfw = 0;
+    float sr[KSS][4], si[KSS][4];                // M-step sums of this lane's rows (FP32)
+#pragma unroll
+    for (int ks = 0; ks < KSS; ++ks)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) sr[ks][e] = si[ks][e] = 0.f;
+    double s64[2] = {0.0, 0.0};                  // two of the lane group's 32 values, FP64
+    double acc_lse = 0.0, acc_wc = 0.0, acc_rows = 0.0;
+    int nfl = 0;
+    // fold the FP32 M-step sums into FP64: sum over the 16 lanes of the group (its 16 rows of
+    // every tile), then lane rl keeps values rl and rl + 16 of the group's 32
+    auto fold = [&]() {
+        float x0 = 0.f, x1 = 0.f;
+#pragma unroll
+        for (int ks = 0; ks < KSS; ++ks)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float a = row16_sum(sr[ks][e]), b = row16_sum(si[ks][e]);
+                const int i = ks * 8 + e * 2;
+                x0 = rl == i ? a : x0;
+                x0 = rl == i + 1 ? b : x0;
+                x1 = rl + 16 == i ? a : x1;
+                x1 = rl + 16 == i + 1 ? b : x1;
+                sr[ks][e] = si[ks][e] = 0.f;
+            }
+        s64[0] += (double)x0;
+        s64[1] += (double)x1;
+    };
+
+    if (nmine > 0) issue(0, 0);
+    if (nmine > 1) issue(1, 1);
+    int b = 0;                                   // buffer of tile j (tile j + 2 reuses j - 1's)
+    for (int64_t j = 0; j < nmine; ++j, b = b == kKrBufs - 1 ? 0 : b + 1) {
+        // this tile's copies have landed (the next tile's stay in flight) ...
+        if (deep && j + 1 < nmine) {
+            if (wave == 0) wait_vm<5>();
+            else wait_vm<4>();
+        } else {
+            wait_vm<0>();
+        }
+        // ... for every wave, and every wave is done with the previous tile's buffer
+        lds_barrier();
+        if (j + 2 < nmine) issue(j + 2, b == 0 ? kKrBufs - 1 : b - 1);
+        const uint8_t *Vs = smem + b * BM * LY.RS;
+        const float *rsv = rsb + b * 64;
+        const int64_t r0 = A.row_begin + (int64_t)blockIdx.x * BM + j * tstride;
+        const int rows = (int)((A.row_end - r0) < BM ? (A.row_end - r0) : BM);
+
+        // ---- a3: this wave's K-slice of the correlations
+        u32x4 af[KSS];
+#pragma unroll
+        for (int ks = 0; ks < KSS; ++ks)
+            af[ks] = *(const u32x4 *)(Vs + rl * LY.RS + (wave * KSS + ks) * 64 + g * 16);
+        f32x4 c4[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) c4[nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        // (formed transposed, template fragments as the A operand: lane 16 g + j ends with row j,
+        // columns 16 nt + 4 g .. 16 nt + 4 g + 3)
+#pragma unroll
+        for (int ks = 0; ks < KSS; ++ks) {
+            const H8 bv = __builtin_bit_cast(H8, af[ks]);
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                if constexpr (P == P_F16) {
+                    c4[nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                        __builtin_bit_cast(H8, treg[ks][nt][1]), bv, c4[nt], 0, 0, 0);
+                    c4[nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                        __builtin_bit_cast(H8, treg[ks][nt][0]), bv, c4[nt], 0, 0, 0);
+                } else {
+                    c4[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        __builtin_bit_cast(H8, treg[ks][nt][1]), bv, c4[nt], 0, 0, 0);
+                    c4[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        __builtin_bit_cast(H8, treg[ks][nt][0]), bv, c4[nt], 0, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+            red[(wave * 4 + nt) * kKrRedTile + 17 * g + rl] = c4[nt];
+        lds_barrier();
+
+        // ---- a4 (waves 0-3): rows 4 wave .. 4 wave + 3, 16 lanes per row, columns 4 x .. 4 x + 3
+        // per lane (x = lane % 16): the 8 partial sums in wave order, the log-sum-exp by 16-lane
+        // DPP reductions, the posteriors written as 16-bit hi + lo planes
+        if (wave < 4) {
+            const int r = 4 * wave + (lane >> 4);
+            const bool rv = r < rows;
+            float l[4], e[4];
+            const float4 lr4 = *(const float4 *)(lrs + 4 * px);
+            const bool cok[4] = {4 * px < W, 4 * px + 1 < W, 4 * px + 2 < W, 4 * px + 3 < W};
+            {
+                f32x4 v = red[(0 * 4 + pnt) * kKrRedTile + 17 * pg + r];
+#pragma unroll
+                for (int w2 = 1; w2 < 8; ++w2) v += red[(w2 * 4 + pnt) * kKrRedTile + 17 * pg + r];
+                const float rf = ct * rsv[r];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    l[q] = (rv && cok[q]) ? v[q] * rf + (&lr4.x)[q] : -INFINITY;
+            }
+            float lse;
+            if (A.flags & PF_LOAD_LSE) {
+                lse = rv ? (float)A.lse[r0 + r] : 0.f;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) e[q] = __expf(l[q] - lse);
+            } else {
+                float mx = row16_max(fmaxf(fmaxf(l[0], l[1]), fmaxf(l[2], l[3])));
+                if (!rv) mx = 0.f;                         // (an empty row: every l is -inf)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) e[q] = __expf(l[q] - mx);   // exp(-inf) = 0
+                const float sx = row16_sum((e[0] + e[1]) + (e[2] + e[3]));
+                lse = mx + __logf(sx);
+                const float is = rv ? __builtin_amdgcn_rcpf(sx) : 0.f;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) e[q] *= is;
+            }
+            // e[] are the posteriors; sum_i w_i (l_i - log rho_i) for the per-row sum of w C
+            float wcs = 0.f;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) wcs += e[q] > 0.f ? e[q] * (l[q] - (&lr4.x)[q]) : 0.f;
+            wcs = row16_sum(wcs);
+            {
+                H hv[4], gv[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    hv[q] = (H)e[q];
+                    gv[q] = (H)(e[q] - (float)hv[q]);
+                    accW[q] += e[q];
+                }
+                *(uint2 *)(wsh + r * kKrWS + 8 * px) = __builtin_bit_cast(uint2, hv);
+                *(uint2 *)(wsh + BM * kKrWS + r * kKrWS + 8 * px) = __builtin_bit_cast(uint2, gv);
+            }
+            if (rv && px == 0) {
+                acc_lse += (double)lse;
+                acc_wc += (double)wcs;
+                acc_rows += 1.0;
+                if (A.flags & PF_STORE_LSE) A.lse[r0 + r] = (double)lse;
+            }
+            if constexpr (query) {
+                // argmax (lowest column among equal maxima) and the gap to the runner-up
+                const float m1 = row16_max(fmaxf(fmaxf(e[0], e[1]), fmaxf(e[2], e[3])));
+                int idx = 1 << 30;
+#pragma unroll
+                for (int q = 3; q >= 0; --q)
+                    if (cok[q] && e[q] == m1) idx = 4 * px + q;
+#pragma unroll
+                for (int o = 1; o < 16; o <<= 1) idx = min(idx, __shfl_xor(idx, o));
+                float m2 = 0.f;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (4 * px + q != idx) m2 = fmaxf(m2, e[q]);
+                m2 = row16_max(m2);
+                if (rv) {
+                    const int64_t o = r0 + r - A.row_begin;
+                    if (A.post)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            if (cok[q]) A.post[o * W + 4 * px + q] = e[q];
+                    if (px == 0) {
+                        if (A.argmax) A.argmax[o] = idx;
+                        if (A.margin) A.margin[o] = m1 - m2;
+                    }
+                }
+            }
+            if (++nfw == kKrFlush) {                       // W_t sums: FP32 over 16 tiles
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    wacc[q] += (double)accW[q];
+                    accW[q] = 0.f;
+                }
+                nfw = 0;
+            }
+        }
+        if (!accm) continue;
+        lds_barrier();
+
+        // ---- a5: U^T for this wave's frequencies, then the M-step on the wave's fragments
+        f32x4 u4 = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const H8 bh = *(const H8 *)(wsh + rl * kKrWS + (32 * s + 8 * g) * 2);
+            const H8 bl = *(const H8 *)(wsh + BM * kKrWS + rl * kKrWS + (32 * s + 8 * g) * 2);
+            if constexpr (P == P_F16) {
+                u4 = __builtin_amdgcn_mfma_f32_16x16x32_f16(el[s], bh, u4, 0, 0, 0);
+                u4 = __builtin_amdgcn_mfma_f32_16x16x32_f16(eh[s], bl, u4, 0, 0, 0);
+                u4 = __builtin_amdgcn_mfma_f32_16x16x32_f16(eh[s], bh, u4, 0, 0, 0);
+            } else {
+                u4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(el[s], bh, u4, 0, 0, 0);
+                u4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(eh[s], bl, u4, 0, 0, 0);
+                u4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(eh[s], bh, u4, 0, 0, 0);
+            }
+        }
+        // u4[q] = U[row rl][column 4 g + q] (before the row's storage scale)
+        *(f32x4 *)(up + rl * kKrUS + 4 * g) = u4 * (rl < rows ? rsv[rl] : 0.f);
+        asm volatile("" ::: "memory");           // a wave's LDS accesses complete in order
+#pragma unroll
+        for (int ks = 0; ks < KSS; ++ks) {
+            const float2 U = *(const float2 *)(up + rl * kKrUS + um[ks]);
+            const H8 v8 = __builtin_bit_cast(H8, af[ks]);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float vr = (float)v8[2 * e], vi = (float)v8[2 * e + 1];
+                sr[ks][e] = fmaf(U.x, vr, fmaf(-U.y, vi, sr[ks][e]));
+                si[ks][e] = fmaf(U.x, vi, fmaf(U.y, vr, si[ks][e]));
+            }
+        }
+        if (++nfl == kKrFlush) {
+            fold();
+            nfl = 0;
+        }
+    }
+    fold();
+    if (wave < 4)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) wacc[q] += (double)accW[q];
+
+    // ---- per-workgroup partials: S (2D), W_t (Wp), sum lse', sum w C, rows
+    __syncthreads();
+    const double *wsum = (const double *)(smem + LY.off_wacc);   // [16 row lanes][64 columns]
+    if (A.partials) {
+        double *Pp = A.partials + (int64_t)blockIdx.x * A.ncols;
+        // value i of lane group g (i = 8 ks + 2 e + re/im) is real 2 d + (i & 1) of S, d = 16 (4
+        // wave + ks) + 4 g + e
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+            const int i = rl + 16 * x, ks = i >> 3, e = (i >> 1) & 3;
+            const int d = 16 * (wave * KSS + ks) + 4 * g + e;
+            if (d < D) Pp[2 * d + (i & 1)] = accm ? s64[x] : 0.0;
+        }
+        if (tid < Wp) {
+            double t = 0.0;
+            for (int k = 0; k < 16; ++k) t += wsum[k * 64 + tid];
+            Pp[2 * D + tid] = accm ? t : 0.0;
+        }
+        __syncthreads();
+        double *sh = (double *)smem;
+        const double s_lse = block_sum_d(acc_lse, sh, kThreads);
+        const double s_wc = block_sum_d(acc_wc, sh, kThreads);
+        const double s_rows = block_sum_d(acc_rows, sh, kThreads);
+        if (tid == 0) {
+            Pp[2 * D + Wp] = s_lse;
+            Pp[2 * D + Wp + 1] = s_wc / A.coef;
+            Pp[2 * D + Wp + 2] = s_rows;
+            Pp[2 * D + Wp + 3] = 0.0;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Long-window FP32 correlation pass (full search over L rotations: the baseline the windowed
+// forms are compared against), built as a matrix-core GEMM with the posterior and M-step as its
+// epilogue.  A workgroup takes 128-row tiles; wave w owns the 16 rows 16 w .. 16 w + 15 and all
+// Wp window columns of them (NTC 16-column tiles of accumulators).  The contraction over the 2D
+// reals runs in 32-real chunks: each chunk's rows (16 KiB, 16-byte slots XOR-swizzled per row
+// pair so that the fragment reads are conflict-free) and template rows (NTC x 2 KiB, in the
+// template's fragment order) are copied global-to-LDS one chunk ahead into a double buffer.  The
+// correlations are formed transposed (template fragments as the A operand, rows as B), so a lane
+// ends with 4 NTC window columns of one row: the log-sum-exp and the posteriors need only its own
+// registers and a reduction over the four lanes of the row.  Epilogue per tile:
+//   * W_t: 16-lane DPP sums of the posteriors over the wave's rows, added over the waves in wave
+//     order through LDS into one FP64 accumulator per column;
+//   * U^T = E'^T w^T on matrix cores straight from the posterior registers (the contraction over
+//     the window runs in the order the registers hold it; E' staged in LDS), left per wave in LDS;
+//   * M-step on VALU: lane l takes entries 8 l .. 8 l + 7 (one frequency, Q % 8 == 0) of the
+//     wave's 16 rows, re-read from global memory (on-die caches, mostly), FP64 sums per lane.
+// Needs FP32 storage, D <= 512 with Q % 8 == 0, K <= 32 and Wp <= 384.
+
+constexpr int kGmBM = 128;                // rows per tile (8 waves x 16)
+constexpr int kGmKC = 32;                 // reals per contraction chunk
+constexpr int kGmMaxNT = 24;              // window tiles (Wp <= 384)
+
+struct GmLds {
+    int stage, off_t, total_loop, off_e2, off_us, off_wt, off_sw, off_lr, total;
+};
+__host__ __device__ inline GmLds gm_lds(int NTC, int Wp, int K, int D) {
+    GmLds l;
+    const int vbytes = kGmBM * kGmKC * 4;                 // 16 KiB of rows per chunk
+    l.off_t = vbytes;                                     // then NTC x 2 KiB of template
+    l.stage = vbytes + NTC * 2 * 1024;
+    l.total_loop = 2 * l.stage;
+    // epilogue (the chunk buffers are idle then): E' (Wp x 2K floats), U^T blocks (8 waves x
+    // 16 rows x 2K floats), the waves' column sums (8 x Wp floats)
+    l.off_e2 = 0;
+    l.off_us = align_up(((2 * K + 15) / 16) * NTC * 256 * 4, 16);
+    l.off_wt = l.off_us + 8 * 16 * 2 * K * 4;
+    int epi = l.off_wt + 8 * Wp * 4;
+    // the waves' FP32 M-step sums (8 x 2D floats) go where E' was once it is consumed, unless
+    // that area is too small (then after the column sums)
+    const int swb = 8 * 2 * D * 4;
+    l.off_sw = swb <= l.off_us ? 0 : align_up(epi, 16);
+    if (l.off_sw) epi = l.off_sw + swb;
+    l.off_lr = align_up(epi > l.total_loop ? epi : l.total_loop, 16);
+    l.total = l.off_lr + Wp * 4 + 16;
+    return l;
+}
+
+// s_waitcnt vmcnt(n) for a run-time n in [0, 15]
+__device__ __forceinline__ void wait_vm_rt(int n) {
+    switch (n) {
+    case 0: wait_vm<0>(); break;
+    case 1: wait_vm<1>(); break;
+    case 2: wait_vm<2>(); break;
+    case 3: wait_vm<3>(); break;
+    case 4: wait_vm<4>(); break;
+    case 5: wait_vm<5>(); break;
+    case 6: wait_vm<6>(); break;
+    case 7: wait_vm<7>(); break;
+    case 8: wait_vm<8>(); break;
+    case 9: wait_vm<9>(); break;
+    default: wait_vm<0>(); break;
+    }
+}
+
+template <int NTC, int QRY>
+__global__ __launch_bounds__(kThreads) void pass_gm_kernel(PassArgs A) {
+    static_assert(NTC >= 1 && NTC <= kGmMaxNT, "window tiles");
+    constexpr bool query = QRY != 0;
+    if ((A.flags & PF_CHECK_STOP) && *A.stopped) return;
+
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int g = lane >> 4, j = lane & 15;
+    const int D = A.D, K = A.K, W = A.W, Wp = A.Wp, K2 = 2 * A.K;
+    const GmLds LY = gm_lds(NTC, Wp, K, D);
+    float *lrs = (float *)(smem + LY.off_lr);
+    for (int i = tid; i < Wp; i += kThreads) lrs[i] = A.logrho32[i];
+    const float coef = (float)A.coef;
+    const int NCH = A.Dp / kGmKC;                         // chunks per row
+    const int KG = A.Dp / 16;                             // template k-groups per column tile
+    // copies per wave per chunk: two 1 KiB row slices, and template slices w, w + 8, .. < 2 NTC
+    const int ncopy = 2 + (2 * NTC + 7 - wave) / 8;
+    const int64_t ntiles = (A.row_end - A.row_begin + kGmBM - 1) / kGmBM;
+
+    // FP64 sums kept by thread t: M-step reals t and t + 512 (2D <= 1024), W_t column t
+    double S64[2] = {0.0, 0.0};
+    double Wacc = 0.0, acc_lse = 0.0, acc_wc = 0.0, acc_rows = 0.0;
+    __syncthreads();
+
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t r0 = A.row_begin + tile * kGmBM;
+        auto issue = [&](int c) {
+            uint8_t *st = smem + (c & 1) * LY.stage;
+            // rows: LDS slot p (16 B) of the chunk holds row p / 8, real slot (p % 8) ^ ((row >>
+            // 1) & 7); wave w copies slots 64 (w + 8 x) .. + 63
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                const int p = 64 * (wave + 8 * x) + lane, r = p >> 3;
+                const int sl = (p & 7) ^ ((r >> 1) & 7);
+                const int64_t row = r0 + r < A.row_end ? r0 + r : A.row_end - 1;
+                dma_to_lds<16>(A.V + row * A.rowbytes + (c * kGmKC + 4 * sl) * 4,
+                               st + 64 * (wave + 8 * x) * 16);
+            }
+            // template: slice s = 2 nt + kk is k-group 2 c + kk of column tile nt (1 KiB)
+            for (int s = wave; s < 2 * NTC; s += 8) {
+                const int nt = s >> 1, kg = 2 * c + (s & 1);
+                dma_to_lds<16>((const float *)A.Thi + (((int64_t)nt * KG + kg) * 64 + lane) * 4,
+                               st + LY.off_t + s * 1024);
+            }
+        };
+        // ---- a3: C^T for this wave's 16 rows over all window columns
+        f32x4 acc[NTC];
+#pragma unroll
+        for (int t = 0; t < NTC; ++t) acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        issue(0);
+        const int rr = 16 * wave + j;                     // this lane's row in the tile
+        for (int c = 0; c < NCH; ++c) {
+            wait_vm<0>();                                 // chunk c has landed (this wave's part)
+            lds_barrier();                                // ... all of it; chunk c - 1 is consumed
+            if (c + 1 < NCH) issue(c + 1);                // into the buffer chunk c - 1 used
+            const uint8_t *st = smem + (c & 1) * LY.stage;
+#pragma unroll
+            for (int kk = 0; kk < 2; ++kk) {
+                const int sl = (4 * kk + g) ^ ((rr >> 1) & 7);
+                const float4 b = *(const float4 *)(st + rr * 128 + sl * 16);
+#pragma unroll
+                for (int t = 0; t < NTC; ++t) {
+                    const float4 a = *(const float4 *)(st + LY.off_t + (2 * t + kk) * 1024 + lane * 16);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc[t], 0, 0, 0);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc[t], 0, 0, 0);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc[t], 0, 0, 0);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc[t], 0, 0, 0);
+                }
+            }
+        }
+        // acc[t][q] = C[row rr][column 16 t + 4 g + q]
+        lds_barrier();                                    // the chunk buffers are free now
+        // stage E' for the U product in the order its A operands are read: entry (mt, t, q, lane)
+        // = E2[16 t + 4 (lane / 16) + q][16 mt + lane % 16] (zero past 2K)
+        {
+            float *e2s = (float *)(smem + LY.off_e2);
+            const int MTs = (K2 + 15) / 16, n = MTs * NTC * 4 * 64;
+            for (int x = tid; x < n; x += kThreads) {
+                const int ln = x & 63, q = (x >> 6) & 3, t = (x >> 8) % NTC, mt = (x >> 8) / NTC;
+                const int col = 16 * mt + (ln & 15), i = 16 * t + 4 * (ln >> 4) + q;
+                e2s[x] = col < K2 ? A.E2[i * K2 + col] : 0.f;
+            }
+        }
+        const int64_t row = r0 + rr;
+        const bool rv = row < A.row_end;
+
+        // ---- a4: log-weights, log-sum-exp over the row's 4 lanes, posteriors (in acc)
+        float mx = -INFINITY;
+#pragma unroll
+        for (int t = 0; t < NTC; ++t)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int col = 16 * t + 4 * g + q;
+                const float l = (col < W && rv) ? acc[t][q] * coef + lrs[col] : -INFINITY;
+                acc[t][q] = l;
+                mx = fmaxf(mx, l);
+            }
+        mx = fmaxf(mx, swz_xor16(mx));
+        mx = fmaxf(mx, __shfl_xor(mx, 32));
+        float lse;
+        if (A.flags & PF_LOAD_LSE) {
+            lse = rv ? (float)A.lse[row] : 0.f;
+        } else {
+            float s = 0.f;
+#pragma unroll
+            for (int t = 0; t < NTC; ++t)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) s += __expf(acc[t][q] - mx);   // exp(-inf) = 0
+            s += swz_xor16(s);
+            s += __shfl_xor(s, 32);
+            lse = mx + __logf(s);
+        }
+        float wc = 0.f, m1 = 0.f;
+#pragma unroll
+        for (int t = 0; t < NTC; ++t)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int col = 16 * t + 4 * g + q;
+                const float l = acc[t][q];
+                const float w = rv ? __expf(l - lse) : 0.f;
+                if (w > 0.f) wc += w * (l - lrs[col]);
+                m1 = fmaxf(m1, w);
+                acc[t][q] = w;
+            }
+        wc += swz_xor16(wc);
+        wc += __shfl_xor(wc, 32);
+        if (rv && g == 0) {
+            acc_lse += (double)lse;
+            acc_wc += (double)wc;
+            acc_rows += 1.0;
+            if (A.flags & PF_STORE_LSE) A.lse[row] = (double)lse;
+        }
+        if constexpr (query) {
+            // argmax (lowest column among equal maxima) and the gap to the runner-up
+            m1 = fmaxf(m1, swz_xor16(m1));
+            m1 = fmaxf(m1, __shfl_xor(m1, 32));
+            int idx = 1 << 30;
+#pragma unroll
+            for (int t = NTC - 1; t >= 0; --t)
+#pragma unroll
+                for (int q = 3; q >= 0; --q)
+                    if (acc[t][q] == m1 && 16 * t + 4 * g + q < W) idx = 16 * t + 4 * g + q;
+            idx = min(idx, __shfl_xor(idx, 16));
+            idx = min(idx, __shfl_xor(idx, 32));
+            float m2 = 0.f;
+#pragma unroll
+            for (int t = 0; t < NTC; ++t)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (16 * t + 4 * g + q != idx) m2 = fmaxf(m2, acc[t][q]);
+            m2 = fmaxf(m2, swz_xor16(m2));
+            m2 = fmaxf(m2, __shfl_xor(m2, 32));
+            if (rv) {
+                const int64_t o = row - A.row_begin;
+                if (A.post) {
+#pragma unroll
+                    for (int t = 0; t < NTC; ++t)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            if (16 * t + 4 * g + q < W) A.post[o * W + 16 * t + 4 * g + q] = acc[t][q];
+                }
+                if (g == 0) {
+                    if (A.argmax) A.argmax[o] = idx;
+                    if (A.margin) A.margin[o] = m1 - m2;
+                }
+            }
+        }
+        if (!(A.flags & PF_ACC_M)) {
+            __syncthreads();                              // before the next tile's copies
+            continue;
+        }
+
+        // ---- W_t: column sums over the wave's 16 rows (DPP), then over the waves in order
+        float *wt = (float *)(smem + LY.off_wt);
+#pragma unroll
+        for (int t = 0; t < NTC; ++t)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float s = row16_sum(acc[t][q]);
+                if (((4 * t + q) & 15) == j) wt[wave * Wp + 16 * t + 4 * g + q] = s;
+            }
+        // ---- a5: U^T = E'^T w^T, contraction over the window in register order: k-step (t, q)
+        // pairs lane group g with window column 16 t + 4 g + q
+        const float *e2s = (const float *)(smem + LY.off_e2);
+        float *us = (float *)(smem + LY.off_us) + wave * 16 * K2;
+        lds_barrier();                                    // E' staged, column sums written
+        if (tid < Wp) {
+            float s = 0.f;
+            for (int w2 = 0; w2 < 8; ++w2) s += wt[w2 * Wp + tid];
+            Wacc += (double)s;
+        }
+        const int MT = (K2 + 15) / 16;
+        for (int mt = 0; mt < MT; ++mt) {
+            const float *ep = e2s + mt * NTC * 256 + lane;
+            f32x4 u4 = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int t = 0; t < NTC; ++t)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    u4 = __builtin_amdgcn_mfma_f32_16x16x4f32(ep[(4 * t + q) * 64], acc[t][q], u4,
+                                                              0, 0, 0);
+            // u4[q] = U[row j][16 mt + 4 g + q]
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (16 * mt + 4 * g + q < K2) us[j * K2 + 16 * mt + 4 * g + q] = u4[q];
+        }
+        asm volatile("" ::: "memory");                    // a wave's LDS accesses complete in order
+        // M-step: entries d = 8 lane + e of the wave's 16 rows (FP32 over the 16 rows), then the
+        // waves' sums added in wave order into the FP64 sums (E' staging area reused)
+        float *swv = (float *)(smem + LY.off_sw);         // 8 waves x 2D floats
+        lds_barrier();                                    // every wave is done reading E'
+        if (8 * lane < D) {
+            const int k = (8 * lane) / A.Q;
+            float sr[8], si[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) sr[e] = si[e] = 0.f;
+#pragma unroll 4
+            for (int jr = 0; jr < 16; ++jr) {
+                const int64_t rw = r0 + 16 * wave + jr;
+                const int64_t rc = rw < A.row_end ? rw : A.row_end - 1;
+                const float4 *src = (const float4 *)(A.V + rc * A.rowbytes) + 4 * lane;
+                float4 v[4];
+#pragma unroll
+                for (int x = 0; x < 4; ++x) v[x] = src[x];
+                const float ur = us[jr * K2 + k], ui = us[jr * K2 + K + k];   // 0 past the end
+#pragma unroll
+                for (int x = 0; x < 4; ++x) {
+                    sr[2 * x] += ur * v[x].x - ui * v[x].y;
+                    si[2 * x] += ur * v[x].y + ui * v[x].x;
+                    sr[2 * x + 1] += ur * v[x].z - ui * v[x].w;
+                    si[2 * x + 1] += ur * v[x].w + ui * v[x].z;
+                }
+            }
+            float *o = swv + wave * 2 * D + 16 * lane;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                o[2 * e] = sr[e];
+                o[2 * e + 1] = si[e];
+            }
+        }
+        lds_barrier();
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+            const int r = tid + x * kThreads;
+            if (r < 2 * D) {
+                float s8 = 0.f;
+                for (int w2 = 0; w2 < 8; ++w2) s8 += swv[w2 * 2 * D + r];
+                S64[x] += (double)s8;
+            }
+        }
+        __syncthreads();                                  // LDS reused by the next tile's copies
+    }
+
+    // ---- per-workgroup partials: S (the waves' sums in wave order), W_t, sum lse', sum w C, rows
+    if (A.partials) {
+        double *Pp = A.partials + (int64_t)blockIdx.x * A.ncols;
+        const bool accm = (A.flags & PF_ACC_M) != 0;
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+            const int r = tid + x * kThreads;
+            if (r < 2 * D) Pp[r] = accm ? S64[x] : 0.0;
+        }
+        if (tid < Wp) Pp[2 * D + tid] = accm ? Wacc : 0.0;
+        __syncthreads();
+        double *sh = (double *)smem;
+        const double s_lse = block_sum_d(acc_lse, sh, kThreads);
+        const double s_wc = block_sum_d(acc_wc, sh, kThreads);
+        const double s_rows = block_sum_d(acc_rows, sh, kThreads);
+        if (tid == 0) {
+            Pp[2 * D + Wp] = s_lse;
+            Pp[2 * D + Wp + 1] = s_wc / A.coef;
+            Pp[2 * D + Wp + 2] = s_rows;
+            Pp[2 * D + Wp + 3] = 0.0;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
 // Factored E(+M) pass: the correlations through per-frequency sums, an exact rewrite of the
 // contraction (a rotation is one phase per angular frequency, §I eq. (3)):
 //   Re <v_j, R_{o_i} a> = Re sum_k c_jk exp(-i k theta_i),   c_jk = sum_q conj(v_jkq) a_kq.
@@ -2559,19 +3348,49 @@ constexpr int kFinWaves = kFinThreads / 64;
 constexpr int kRedCols = 16;                       // partial columns per reducing workgroup
 constexpr int kFinPhaseLds = 2048;                 // phase table staged in LDS up to this L
 
-// Deterministic workgroup sums (OP = 0) or maxima (OP = 1) of NV doubles per thread: a butterfly
-// over the wave's 64 lanes (every lane ends with the same value), then the kFinWaves wave results
-// in wave order.  sh holds NV x kFinWaves doubles; every thread must call it.
+// FP64 lane exchanges by DPP on the two 32-bit halves (no LDS round trip), and a lane's value
+// read by every lane of the wave.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double rl_d(double v, int lane) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)(unsigned)u, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+template <int OP>
+__device__ __forceinline__ double fin_op(double a, double b) {
+    return OP ? fmax(a, b) : a + b;
+}
+// Sum (OP = 0) or maximum (OP = 1) over each 16-lane row (xor 1, xor 2, half-mirror, mirror:
+// every lane of the row ends with the same value), then over the wave (rows 0..3 read in order).
+// Every lane must be active.
+template <int OP>
+__device__ __forceinline__ double row16_reduce_d(double v) {
+    v = fin_op<OP>(v, dpp_d<0xB1>(v));
+    v = fin_op<OP>(v, dpp_d<0x4E>(v));
+    v = fin_op<OP>(v, dpp_d<0x141>(v));
+    return fin_op<OP>(v, dpp_d<0x140>(v));
+}
+template <int OP>
+__device__ __forceinline__ double wave_reduce_d(double v) {
+    v = row16_reduce_d<OP>(v);
+    return fin_op<OP>(fin_op<OP>(rl_d(v, 0), rl_d(v, 16)), fin_op<OP>(rl_d(v, 32), rl_d(v, 48)));
+}
+
+// Deterministic workgroup sums (OP = 0) or maxima (OP = 1) of NV doubles per thread: a fixed-order
+// reduction over the wave's 64 lanes (every lane ends with the same value), then the kFinWaves
+// wave results in wave order.  sh holds NV x kFinWaves doubles; every thread must call it.
 template <int NV, int OP = 0>
 __device__ __forceinline__ void fin_block_reduce(double (&v)[NV], double *sh) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int m = 32; m >= 1; m >>= 1)
-#pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            const double o = __shfl_xor(v[k], m);
-            v[k] = OP ? fmax(v[k], o) : v[k] + o;
-        }
+    for (int k = 0; k < NV; ++k) v[k] = wave_reduce_d<OP>(v[k]);
     __syncthreads();
     if (lane == 0)
 #pragma unroll
@@ -2580,10 +3399,28 @@ __device__ __forceinline__ void fin_block_reduce(double (&v)[NV], double *sh) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         double t = sh[k * kFinWaves];
-        for (int w = 1; w < kFinWaves; ++w)
-            t = OP ? fmax(t, sh[k * kFinWaves + w]) : t + sh[k * kFinWaves + w];
+        for (int w = 1; w < kFinWaves; ++w) t = fin_op<OP>(t, sh[k * kFinWaves + w]);
         v[k] = t;
     }
+}
+// One maximum and one sum in the same pass (one pair of barriers).
+__device__ __forceinline__ void fin_block_max_sum(double &mx, double &sm, double *sh) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    mx = wave_reduce_d<1>(mx);
+    sm = wave_reduce_d<0>(sm);
+    __syncthreads();
+    if (lane == 0) {
+        sh[wave] = mx;
+        sh[kFinWaves + wave] = sm;
+    }
+    __syncthreads();
+    double a = sh[0], b = sh[kFinWaves];
+    for (int w = 1; w < kFinWaves; ++w) {
+        a = fmax(a, sh[w]);
+        b += sh[kFinWaves + w];
+    }
+    mx = a;
+    sm = b;
 }
 
 // The finalize proper (one workgroup), on the reduced sums in F.red.
@@ -2691,7 +3528,7 @@ __device__ void finalize_body(const FinArgs &F) {
                       N * (double)D * log(M_PI * F.sigma2);
 
     // c_k = sum_q conj(a_new[k,q]) a_t[k,q]: 16 lanes per k (q = lane % 16, + 16, ...), their
-    // partial sums combined by a butterfly inside the 16-lane group
+    // partial sums combined inside the 16-lane DPP row
     for (int k0 = 0; k0 < K; k0 += kFinThreads / 16) {
         const int k = k0 + t / 16, qp = t % 16;
         double cr = 0.0, ci = 0.0;
@@ -2702,11 +3539,8 @@ __device__ void finalize_body(const FinArgs &F) {
                 cr += a1.x * a0.x + a1.y * a0.y;
                 ci += a1.x * a0.y - a1.y * a0.x;
             }
-#pragma unroll
-        for (int m = 8; m >= 1; m >>= 1) {
-            cr += __shfl_xor(cr, m);
-            ci += __shfl_xor(ci, m);
-        }
+        cr = row16_reduce_d<0>(cr);
+        ci = row16_reduce_d<0>(ci);
         if (k < K && qp == 0) ck[k] = make_double2(cr, ci);
     }
     __syncthreads();
@@ -2743,12 +3577,9 @@ __device__ void finalize_body(const FinArgs &F) {
         if (t + c * kFinThreads < W && rn[c] > 0.0) ent -= rn[c] * log(rn[c]);
     }
     {
-        double mx[1] = {-best};
-        fin_block_reduce<1, 1>(mx, sh);
-        best = -mx[0];
-        double e1[1] = {ent};
-        fin_block_reduce<1>(e1, sh + kFinWaves);
-        ent = e1[0];
+        double mx = -best;
+        fin_block_max_sum(mx, ent, sh);
+        best = -mx;
     }
     // rho_{t+1} and its log (-inf on zero entries and on the padding up to Wp), a_{t+1}
 #pragma unroll
@@ -3035,6 +3866,107 @@ const char *pass_ks_name(int prec, int BM, int NT, int KSS) {
     static thread_local char buf[64];   // (per thread: callers copy it out)
     snprintf(buf, sizeof buf, "pass_ks_kernel<%s,BM=%d,NT=%d,KSS=%d>", kPrecName[prec], BM, NT,
              KSS);
+    return buf;
+}
+
+// Row-stream variants: (precision, window tiles).
+#define SEM_KR_VARIANTS(X)                                                                     \
+    X(P_F16, 1) X(P_F16, 2) X(P_F16, 3) X(P_F16, 4) X(P_BF16, 1) X(P_BF16, 2) X(P_BF16, 3)     \
+    X(P_BF16, 4)
+
+static pass_fn find_kr(int prec, int NT, int QRY = 0) {
+#define SEM_X(P, N)                                                                            \
+    if (prec == P && NT == N) return QRY ? pass_kr_kernel<P, N, 1> : pass_kr_kernel<P, N, 0>;
+    SEM_KR_VARIANTS(SEM_X)
+#undef SEM_X
+    return nullptr;
+}
+
+bool kr_plan(int prec, int D, int Dp, int Q, int Wp, size_t lds_max, int *NT, size_t *lds) {
+    if (prec != P_F16 && prec != P_BF16) return false;
+    if (D != 512 || Dp != 1024) return false;
+    if (Q != 8 && Q != 16 && Q != 32 && Q != 64) return false;
+    const int nt = Wp / 16;
+    if (nt < 1 || nt > 4 || !find_kr(prec, nt)) return false;
+    const size_t l = (size_t)kr_lds(Dp).total;
+    if (l > lds_max) return false;
+    *NT = nt;
+    *lds = l;
+    return true;
+}
+
+hipError_t launch_pass_kr(int prec, int NT, const PassArgs &a, int grid, size_t lds,
+                          hipStream_t s) {
+    pass_fn f = find_kr(prec, NT, (a.flags & PF_QUERY) ? 1 : 0);
+    if (!f) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(f, dim3(grid), dim3(kThreads), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t pass_kr_setup(int prec, int NT, size_t lds, int *blocks_per_cu) {
+    pass_fn f = find_kr(prec, NT);
+    if (!f) return hipErrorInvalidValue;
+    for (int q = 0; q < 2; ++q) {
+        hipError_t e = hipFuncSetAttribute((const void *)find_kr(prec, NT, q),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) (void)hipGetLastError();
+    }
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void *)f, kThreads,
+                                                        lds);
+}
+
+const char *pass_kr_name(int prec, int NT) {
+    static thread_local char buf[64];   // (per thread: callers copy it out)
+    snprintf(buf, sizeof buf, "pass_kr_kernel<%s,NT=%d>", kPrecName[prec], NT);
+    return buf;
+}
+
+// Long-window FP32 GEMM-epilogue variants: (window tiles).
+#define SEM_GM_VARIANTS(X)                                                                     \
+    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)     \
+    X(17) X(18) X(19) X(20) X(21) X(22) X(23) X(24)
+
+static pass_fn find_gm(int NTC, int QRY = 0) {
+#define SEM_X(N)                                                                               \
+    if (NTC == N) return QRY ? pass_gm_kernel<N, 1> : pass_gm_kernel<N, 0>;
+    SEM_GM_VARIANTS(SEM_X)
+#undef SEM_X
+    return nullptr;
+}
+
+bool gm_plan(int prec, int D, int K, int Q, int Wp, size_t lds_max, int *NTC, size_t *lds) {
+    if (prec != P_F32 || D > 512 || Q % 8 != 0 || K > 32) return false;
+    const int nt = Wp / 16;
+    if (nt < 1 || nt > kGmMaxNT || !find_gm(nt)) return false;
+    const size_t l = (size_t)gm_lds(nt, Wp, K, D).total;
+    if (l > lds_max) return false;
+    *NTC = nt;
+    *lds = l;
+    return true;
+}
+
+hipError_t launch_pass_gm(int NTC, const PassArgs &a, int grid, size_t lds, hipStream_t s) {
+    pass_fn f = find_gm(NTC, (a.flags & PF_QUERY) ? 1 : 0);
+    if (!f) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(f, dim3(grid), dim3(kThreads), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t pass_gm_setup(int NTC, size_t lds, int *blocks_per_cu) {
+    pass_fn f = find_gm(NTC);
+    if (!f) return hipErrorInvalidValue;
+    for (int q = 0; q < 2; ++q) {
+        hipError_t e = hipFuncSetAttribute((const void *)find_gm(NTC, q),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) (void)hipGetLastError();
+    }
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void *)f, kThreads,
+                                                        lds);
+}
+
+const char *pass_gm_name(int NTC) {
+    static thread_local char buf[64];   // (per thread: callers copy it out)
+    snprintf(buf, sizeof buf, "pass_gm_kernel<f32,BM=%d,NTC=%d>", kGmBM, NTC);
     return buf;
 }
 

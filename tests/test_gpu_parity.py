@@ -90,8 +90,11 @@ def test_teacher_forced_step(gpu, prec, case):
     print(f"case={case} prec={prec} N={w.N} D={w.D} L={w.L} W={W}", flush=True)
     em = EM(_obs(V, prec, gpu), K=w.K, Q=w.Q, L=w.L, sigma2=s2, window=(lo, W), prior=rb,
             gamma=gamma, precision=prec, gamma_a_inv=gai)
-    if case in ("wide", "kodd") and prec in ("bf16x3", "fp16", "bf16"):
+    if case == "kodd" and prec in ("bf16x3", "fp16", "bf16"):
         assert em.info()["kernel"].startswith("pass_ks_kernel"), em.info()
+    if case == "wide" and prec in ("bf16x3", "fp16", "bf16"):
+        want = "pass_ks_kernel" if prec == "bf16x3" else "pass_kr_kernel"
+        assert em.info()["kernel"].startswith(want), em.info()
     em.set_state(a_t, rho_t, 0)
     _compare_posteriors(em, V, a_t, rho_t, s2, w, lo, W, prec)
     ll_ref = oracle.loglik(V, a_t, rho_t, s2, w.kbar, w.L, oracle.offsets(lo, W))

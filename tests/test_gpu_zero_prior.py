@@ -15,10 +15,12 @@ TOL = {"fp64": dict(post=2e-7, a=1e-10, ll=1e-12), "fp32": dict(post=2e-4, a=2e-
 
 # (precision, EM keyword arguments, kernel family the planner must pick)
 PASSES = [("fp64", {}, "pass_kernel"),
-          ("fp32", {}, "pass_kernel"),
+          ("fp32", {}, "pass_gm_kernel"),
+          ("fp32", {"general_pass": True}, "pass_kernel"),
           ("bf16x3", {"general_pass": True}, "pass_kernel"),
           ("bf16x3", {}, "pass_ks_kernel"),
-          ("fp16", {}, "pass_ks_kernel"),
+          ("fp16", {}, "pass_kr_kernel"),
+          ("fp16", {"staged_pass": True}, "pass_ks_kernel"),
           ("fp32", {"factored": True}, "pass_fac_kernel"),
           ("bf16x3", {"factored": True}, "pass_fac_kernel"),
           ("fp16", {"wide_pass": True}, "pass_wide_kernel")]
