@@ -68,6 +68,7 @@ struct em_ctx {
     double *aE = nullptr, *rhoE = nullptr;
     int64_t *t = nullptr;
     int *stopped = nullptr, *nonfinite = nullptr;
+    unsigned *fin_count = nullptr;     // the reduce-and-finalize launch's done counter
     double *ll_last = nullptr, *stats = nullptr, *partials = nullptr, *red = nullptr;
     double *scal = nullptr;  // [0] ll, [1] grad sigma2
     double *lse = nullptr;
@@ -567,7 +568,10 @@ em_status em_init(em_ctx **out, const em_params *p, const void *obs_dev, const d
     const int64_t ntiles = (c->N + c->BM - 1) / c->BM;
     const int64_t gmax = (int64_t)cus * occ;
     c->grid = (int)(ntiles < gmax ? ntiles : gmax);
-    c->colsum_grid = (int)(c->N < 256 ? c->N : 256);
+    {   // workgroups of the set-up column sums: partials of at most 8 MiB
+        const int64_t cg = 2 * c->D <= 1024 ? 1024 : 256;
+        c->colsum_grid = (int)(c->N < cg ? c->N : cg);
+    }
 
     // buffers
     const int64_t nT = (int64_t)c->Dp * c->Wp;
@@ -595,6 +599,7 @@ em_status em_init(em_ctx **out, const em_params *p, const void *obs_dev, const d
     if ((st = alloc_t(c, &c->gai, (size_t)c->D)) != EM_OK) return bail(st);
     if ((st = alloc_t(c, &c->t, 1)) != EM_OK) return bail(st);
     if ((st = alloc_t(c, &c->stopped, 1)) != EM_OK) return bail(st);
+    if ((st = alloc_t(c, &c->fin_count, 1)) != EM_OK) return bail(st);
     if ((st = alloc_t(c, &c->nonfinite, 1)) != EM_OK) return bail(st);
     if ((st = alloc_t(c, &c->ll_last, 1)) != EM_OK) return bail(st);
     if ((st = alloc_t(c, &c->scal, 4)) != EM_OK) return bail(st);
@@ -661,6 +666,7 @@ em_status em_init(em_ctx **out, const em_params *p, const void *obs_dev, const d
     UP(c->gai, gai.data(), gai.size() * 8);
     UP(c->t, &zero64, 8);
     UP(c->stopped, &zero, 4);
+    UP(c->fin_count, &zero, 4);
     UP(c->nonfinite, &zero, 4);
     UP(c->stats, stats0.data(), stats0.size() * 8);
 
@@ -672,9 +678,9 @@ em_status em_init(em_ctx **out, const em_params *p, const void *obs_dev, const d
     }
     // sum_j ||v_j||^2 (fixed order) and the initial estimate
     {
-        // reduce vnorm2 as a single column over N "blocks"
-        if (launch_reduce(c->vnorm2, (int)std::min<int64_t>(c->N, 1 << 30), 1, c->scal,
-                          c->stream) != hipSuccess) {
+        // in the first G entries of the partials buffer (the column sums below come after)
+        const int G = (int)std::min<int64_t>(c->N, 256);
+        if (launch_sum(c->vnorm2, c->N, c->partials, G, c->scal, c->stream) != hipSuccess) {
             c->err = "reduce launch failed";
             return bail(EM_EDEVICE);
         }
@@ -735,7 +741,8 @@ em_status em_step(em_ctx *c, int32_t n_iter, double tol, int32_t *iters_done, do
         em_status st = run_pass(c, flags, 0, c->N, c->a, c->Thi, c->Tlo, c->tscale, c->logrho32,
                                 c->logrho64, coef, nullptr, nullptr, nullptr, true, true);
         if (st != EM_OK) return st;
-        HIPCHK(c, launch_reduce_finalize(F, c->partials, c->grid, c->ncols, c->red, c->stream));
+        HIPCHK(c, launch_reduce_finalize(F, c->partials, c->grid, c->ncols, c->red, c->fin_count,
+                                         c->stream));
         if (!c->ks && !c->fac && !c->kr)   // these passes use a_t itself
             if ((st = run_template(c, c->a, c->Thi, c->Tlo, c->tscale, true)) != EM_OK) return st;
     }
@@ -758,7 +765,8 @@ em_status em_loglik(em_ctx *c, double *ll) {
                             2.0 / c->sigma2, nullptr, nullptr, nullptr, true, false);
     if (st != EM_OK) return st;
     FinArgs F = fin_base(c, FIN_LL);
-    HIPCHK(c, launch_reduce_finalize(F, c->partials, c->grid, c->ncols, c->red, c->stream));
+    HIPCHK(c, launch_reduce_finalize(F, c->partials, c->grid, c->ncols, c->red, c->fin_count,
+                                         c->stream));
     HIPCHK(c, hipMemcpyAsync(ll, c->scal, 8, hipMemcpyDeviceToHost, c->stream));
     return sync(c);
 }
@@ -832,7 +840,8 @@ em_status em_loglik_fwd(em_ctx *c, const double *a_dev, double sigma2, const dou
     F.sigma2 = sigma2;
     F.a_in = c->aE;
     F.rho_in = c->rhoE;
-    HIPCHK(c, launch_reduce_finalize(F, c->partials, c->grid, c->ncols, c->red, c->stream));
+    HIPCHK(c, launch_reduce_finalize(F, c->partials, c->grid, c->ncols, c->red, c->fin_count,
+                                         c->stream));
     HIPCHK(c, hipMemcpyAsync(ll, c->scal, 8, hipMemcpyDeviceToHost, c->stream));
     if ((st = sync(c)) != EM_OK) return st;
     c->sigma2E = sigma2;
@@ -858,7 +867,8 @@ em_status em_loglik_bwd(em_ctx *c, double g, double *grad_a_dev, double *grad_si
     F.g = g;
     F.grad_a = grad_a_dev;
     F.grad_eta = grad_eta_dev;
-    HIPCHK(c, launch_reduce_finalize(F, c->partials, c->grid, c->ncols, c->red, c->stream));
+    HIPCHK(c, launch_reduce_finalize(F, c->partials, c->grid, c->ncols, c->red, c->fin_count,
+                                         c->stream));
     double gs = 0;
     HIPCHK(c, hipMemcpyAsync(&gs, c->scal + 1, 8, hipMemcpyDeviceToHost, c->stream));
     if ((st = sync(c)) != EM_OK) return st;

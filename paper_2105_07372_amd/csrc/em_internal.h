@@ -108,14 +108,18 @@ hipError_t launch_convert(int prec, const void *obs, int64_t N, int D, int Dp, u
 hipError_t launch_colsum(const void *obs, int is_c128, int64_t N, int D, double *partials,
                          int G, hipStream_t s);
 hipError_t launch_reduce(const double *partials, int G, int ncols, double *out, hipStream_t s);
+// Fixed-order FP64 sum of n values: G workgroup partials (partials holds G doubles), then out.
+hipError_t launch_sum(const double *x, int64_t n, double *partials, int G, double *out,
+                      hipStream_t s);
 hipError_t launch_scale(const double *in, double *out, int n, double factor, hipStream_t s);
 hipError_t launch_template(const TplArgs &a, hipStream_t s);
 hipError_t launch_pass(int prec, int BM, int WM, int LD, const PassArgs &a, int grid, size_t lds,
                        hipStream_t s);
 // The fixed-order sum of G rows of ncols partials into red, then the finalize on red (F.red must
-// be red).
+// be red), in one launch.  count: one device counter per context, 0 before the first launch and
+// left at 0 by every launch; launches that share it must not overlap.
 hipError_t launch_reduce_finalize(const FinArgs &a, const double *partials, int G, int ncols,
-                                  double *red, hipStream_t s);
+                                  double *red, unsigned *count, hipStream_t s);
 // Synchronize and Match (sync_kernels.hip).  B: Lp x K2 floats of cos | sin (see relrot_kernel).
 // true when the 16 x 16 pair-tile kernel serves (2K <= 64, Q % 8 == 0, L <= 384); its cos | sin
 // table then has row stride 64, else 2K rounded up to 4

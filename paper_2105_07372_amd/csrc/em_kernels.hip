@@ -7,8 +7,9 @@
 //                    U_jk = sum_i w_ji exp(+i k theta_i), S_d += sum_j U_{j,kbar_d} v_jd,
 //                    W_i += sum_j w_ji; FP64 per-workgroup partials
 //   reduce_kernel    fixed-order FP64 sum of the partials (set-up sums)
-//   reduce_cols_kernel  the same sum of a pass's partials, more workgroups per column
-//   finalize_kernel  FP64: a_{t+1}, rho_{t+1}, log-likelihood, MAP objective, stopping metric
+//   reduce_finalize_kernel  the same sum of a pass's partials, more workgroups per column; the
+//                    workgroup that finishes last then computes, in FP64, a_{t+1}, rho_{t+1}, the
+//                    log-likelihood, the MAP objective and the stopping metric
 //
 // The per-row constants -(||v_j||^2 + ||a||^2)/sigma^2 - D log(pi sigma^2) of the log-weights are
 // left out of the pass (they cancel in the posteriors) and added back in FP64 in the finalize.
@@ -180,14 +181,54 @@ __global__ __launch_bounds__(512) void colsum_kernel(const void *obs, int is_c12
     const int64_t rpb = (N + gridDim.x - 1) / gridDim.x;
     const int64_t r0 = (int64_t)blockIdx.x * rpb;
     const int64_t r1 = r0 + rpb < N ? r0 + rpb : N;
+    // eight rows in flight per thread (eight running sums, added in a fixed order at the end)
     for (int r = threadIdx.x; r < 2 * D; r += blockDim.x) {
-        double s = 0.0;
-        for (int64_t j = r0; j < r1; ++j) {
-            s += is_c128 ? ((const double *)obs)[j * 2 * D + r]
-                         : (double)((const float *)obs)[j * 2 * D + r];
+        double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int64_t j = r0;
+        for (; j + 8 <= r1; j += 8) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                s[u] += is_c128 ? ((const double *)obs)[(j + u) * 2 * D + r]
+                                : (double)((const float *)obs)[(j + u) * 2 * D + r];
         }
-        partials[(int64_t)blockIdx.x * 2 * D + r] = s;
+        for (int u = 0; j < r1; ++j, ++u)
+            s[u] += is_c128 ? ((const double *)obs)[j * 2 * D + r]
+                            : (double)((const float *)obs)[j * 2 * D + r];
+        partials[(int64_t)blockIdx.x * 2 * D + r] =
+            ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
     }
+}
+
+// Fixed-order FP64 sum of n values in two stages: workgroup b sums the contiguous range
+// [b n / G, (b + 1) n / G) (eight strided running sums per thread, then a tree over the block)
+// into partials[b]; sum_kernel2 adds the G partials in a fixed order.
+__global__ __launch_bounds__(256) void sum_kernel(const double *x, int64_t n, double *partials) {
+    __shared__ double sh[256];
+    const int64_t b0 = n * blockIdx.x / gridDim.x, b1 = n * (blockIdx.x + 1) / gridDim.x;
+    double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int64_t i = b0 + threadIdx.x;
+    for (; i + 7 * 256 < b1; i += 8 * 256) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s[u] += x[i + u * 256];
+    }
+    for (int u = 0; i < b1; i += 256, ++u) s[u] += x[i];
+    double v = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = sh[0];
+}
+// One wave: lane l adds partials l, l + 64, ... in order, then a butterfly over the wave.
+__global__ __launch_bounds__(64) void sum_kernel2(const double *partials, int G, double *out) {
+    const int l = threadIdx.x;
+    double t = 0.0;
+    for (int b = l; b < G; b += 64) t += partials[b];
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) t += __shfl_xor(t, m, 64);
+    if (l == 0) *out = t;
 }
 
 // Fixed-order FP64 reduction over workgroup partials: out[c] = sum_b partials[b][c].
@@ -3340,13 +3381,12 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
 }
 
 // ------------------------------------------------------------------------------------------
-// a6: FP64 reduction of the workgroup partials (reduce_cols_kernel: kRedCols columns per
-// workgroup, all G rows in a fixed order), then the FP64 finalize in one workgroup.
+// a6: FP64 reduction of the workgroup partials (kRedCols columns per workgroup, all G rows in a
+// fixed order), then the FP64 finalize in the workgroup that finishes last (one launch).
 
 constexpr int kFinThreads = 512;
 constexpr int kFinWaves = kFinThreads / 64;
-constexpr int kRedCols = 16;                       // partial columns per reducing workgroup
-constexpr int kFinPhaseLds = 2048;                 // phase table staged in LDS up to this L
+constexpr int kRedCols = 8;                        // partial columns per reducing workgroup
 
 // FP64 lane exchanges by DPP on the two 32-bit halves (no LDS round trip), and a lane's value
 // read by every lane of the wave.
@@ -3423,20 +3463,25 @@ __device__ __forceinline__ void fin_block_max_sum(double &mx, double &sm, double
     sm = b;
 }
 
+// A reduced sum, read at device scope: the other workgroups of the reducing launch wrote it with
+// device-scope stores, so the read skips this CU's caches.
+__device__ __forceinline__ double ld_red(const double *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // The finalize proper (one workgroup), on the reduced sums in F.red.
 __device__ void finalize_body(const FinArgs &F) {
     __shared__ double sh[8 * kFinWaves];
     __shared__ double2 anew[kMaxD];
     __shared__ double2 ain[kMaxD];
     __shared__ double2 ck[kMaxK];
-    __shared__ double2 ph[kFinPhaseLds];
     const int t = threadIdx.x;
     const int D = F.D, W = F.W, K = F.K, L = F.L;
     const double N = (double)F.N;
     const double *S = F.red;
     const double *Wt = F.red + 2 * D;
-    const double s_lse = F.red[2 * D + F.Wp];
-    const double s_wc = F.red[2 * D + F.Wp + 1];
+    const double s_lse = ld_red(F.red + 2 * D + F.Wp);
+    const double s_wc = ld_red(F.red + 2 * D + F.Wp + 1);
 
     if (F.mode != FIN_EM) {
         double v[1] = {0.0};
@@ -3450,10 +3495,11 @@ __device__ void finalize_body(const FinArgs &F) {
             return;
         }
         const double c = F.g * 2.0 / F.sigma2;
-        for (int r = t; r < 2 * D; r += kFinThreads) F.grad_a[r] = c * (S[r] - N * F.a_in[r]);
+        for (int r = t; r < 2 * D; r += kFinThreads)
+            F.grad_a[r] = c * (ld_red(S + r) - N * F.a_in[r]);
         if (F.grad_eta)
             for (int i = t; i < W; i += kFinThreads)
-                F.grad_eta[i] = F.g * (Wt[i] - N * F.rho_in[i]);
+                F.grad_eta[i] = F.g * (ld_red(Wt + i) - N * F.rho_in[i]);
         if (t == 0) {
             const double swr = F.sum_vn2 + N * an2 - 2.0 * s_wc;
             F.out[0] = ll;
@@ -3462,14 +3508,10 @@ __device__ void finalize_body(const FinArgs &F) {
         return;
     }
 
-    // FIN_EM.  Every input (a_t, S, the prior terms, W_t, the phase table, t, the stop flag) is
+    // FIN_EM.  Every input (a_t, S, the prior terms, W_t, the first phase, t, the stop flag) is
     // loaded up front, so the workgroup waits on global memory once.
     constexpr int DPF = kMaxD / kFinThreads, WPF = kMaxWp / kFinThreads;
-    const bool ph_lds = L <= kFinPhaseLds;
-    if (ph_lds) {
-#pragma unroll 4
-        for (int m = t; m < L; m += kFinThreads) ph[m] = F.phase[m];
-    }
+    const double2 ph0 = t < L ? F.phase[t] : make_double2(1.0, 0.0);
     double2 at[DPF], sd[DPF];
     double gv[DPF];
 #pragma unroll
@@ -3479,7 +3521,7 @@ __device__ void finalize_body(const FinArgs &F) {
         gv[c] = 0.0;
         if (d < D) {
             at[c] = ((const double2 *)F.a_in)[d];
-            sd[c] = ((const double2 *)S)[d];
+            sd[c] = make_double2(ld_red(S + 2 * d), ld_red(S + 2 * d + 1));
             if (F.gai) gv[c] = F.gai[d];
         }
     }
@@ -3490,7 +3532,7 @@ __device__ void finalize_body(const FinArgs &F) {
         wt[c] = rb[c] = 0.0;
         ri[c] = 1.0;
         if (i < W) {
-            wt[c] = Wt[i];
+            wt[c] = ld_red(Wt + i);
             rb[c] = F.rho_bar[i];
             ri[c] = F.rho_in[i];
         }
@@ -3504,8 +3546,8 @@ __device__ void finalize_body(const FinArgs &F) {
 #pragma unroll
     for (int c = 0; c < DPF; ++c) {
         const int d = t + c * kFinThreads;
-        const double den = N + F.sigma2 * gv[c];
-        an[c] = make_double2(sd[c].x / den, sd[c].y / den);
+        const double rden = 1.0 / (N + F.sigma2 * gv[c]);
+        an[c] = make_double2(sd[c].x * rden, sd[c].y * rden);
         if (d < D) {
             const double ar = at[c].x, ai = at[c].y;
             anew[d] = an[c];
@@ -3544,36 +3586,28 @@ __device__ void finalize_body(const FinArgs &F) {
         if (k < K && qp == 0) ck[k] = make_double2(cr, ci);
     }
     __syncthreads();
-    // stopping metric min_l ||a_new - exp(-2 pi i kbar l / L) a_t||^2 and the entropy of rho_{t+1}
-    // (the phase table read from LDS or, for L above kFinPhaseLds, from global memory: two loops,
-    // so that neither reads through a generic pointer)
+    // stopping metric min_l ||a_new - exp(-2 pi i kbar l / L) a_t||^2 and the entropy of rho_{t+1}:
+    // Re sum_k c_k z^k at z = exp(-2 pi i l / L) by Horner's rule (|z| = 1, so the rounding error
+    // stays within about 2 K eps sum_k |c_k|), one rotation per thread
     double best = INFINITY;
     for (int l = t; l < L; l += kFinThreads) {
-        double re = 0.0;
-        int m = 0;                                          // (k l) mod L, incrementally
-        if (ph_lds) {
-#pragma unroll 8
-            for (int k = 0; k < K; ++k) {
-                const double2 p = ph[m];                     // exp(+2 pi i k l / L)
-                re += ck[k].x * p.x + ck[k].y * p.y;         // Re(c_k exp(-2 pi i k l / L))
-                m += l;
-                if (m >= L) m -= L;
-            }
-        } else {
-#pragma unroll 8
-            for (int k = 0; k < K; ++k) {
-                const double2 p = F.phase[m];
-                re += ck[k].x * p.x + ck[k].y * p.y;
-                m += l;
-                if (m >= L) m -= L;
-            }
+        const double2 p = l == t ? ph0 : F.phase[l];          // exp(+2 pi i l / L)
+        const double zx = p.x, zy = -p.y;
+        double hx = ck[K - 1].x, hy = ck[K - 1].y;
+#pragma unroll 4
+        for (int k = K - 2; k >= 0; --k) {
+            const double2 c = ck[k];
+            const double nx = fma(hx, zx, fma(-hy, zy, c.x));
+            hy = fma(hx, zy, fma(hy, zx, c.y));
+            hx = nx;
         }
-        best = fmin(best, nn2 + an2 - 2.0 * re);
+        best = fmin(best, nn2 + an2 - 2.0 * hx);
     }
+    const double rtot = 1.0 / tot;
     double rn[WPF], ent = 0.0;
 #pragma unroll
     for (int c = 0; c < WPF; ++c) {
-        rn[c] = F.update_rho ? (wt[c] + F.gamma * rb[c]) / tot : ri[c];
+        rn[c] = F.update_rho ? (wt[c] + F.gamma * rb[c]) * rtot : ri[c];
         if (t + c * kFinThreads < W && rn[c] > 0.0) ent -= rn[c] * log(rn[c]);
     }
     {
@@ -3611,14 +3645,21 @@ __device__ void finalize_body(const FinArgs &F) {
     }
 }
 
-// Fixed-order FP64 sum of a pass's partials: workgroup b sums columns [16 b, 16 b + 16) over the G
-// rows.  Thread t = 16 g + c takes column c of rows g, g + 32, ...; the four row groups of a wave
-// are combined by a butterfly (lanes 16 apart, then 32), then the eight waves in order.
-__global__ __launch_bounds__(kFinThreads) void reduce_cols_kernel(FinArgs F, const double *partials,
-                                                                  int G, int ncols, double *red) {
+// Fixed-order FP64 sum of a pass's partials: workgroup b sums columns [8 b, 8 b + 8) over the G
+// rows.  Thread t = 8 g + c takes column c of rows g, g + 64, ...; the eight row groups of a wave
+// are combined by a butterfly (lanes 8 apart, then 16, then 32), then the eight waves in order.  Each
+// workgroup then counts itself done on *count (atomicInc wraps it back to 0 on the last one, so
+// no clearing is needed between launches); the last runs the finalize on the sums.  With the
+// stop flag set every workgroup leaves before counting.
+__global__ __launch_bounds__(kFinThreads) void reduce_finalize_kernel(FinArgs F,
+                                                                      const double *partials,
+                                                                      int G, int ncols,
+                                                                      double *red,
+                                                                      unsigned *count) {
     __shared__ double rsh[kFinWaves * kRedCols];
+    __shared__ int last;
     constexpr int NG = kFinThreads / kRedCols;
-    static_assert(kRedCols == 16 && NG == 32, "row groups: 4 per wave");
+    static_assert(kRedCols == 8 && NG == 64, "row groups: 8 per wave");
     const int t = threadIdx.x, cl = t % kRedCols, gs = t / kRedCols, wave = t >> 6;
     const int col = blockIdx.x * kRedCols + cl;
     double s = 0.0;
@@ -3626,6 +3667,7 @@ __global__ __launch_bounds__(kFinThreads) void reduce_cols_kernel(FinArgs F, con
 #pragma unroll 8
         for (int b = gs; b < G; b += NG) s += partials[(int64_t)b * ncols + col];
     }
+    s += __shfl_xor(s, 8);
     s += __shfl_xor(s, 16);
     s += __shfl_xor(s, 32);
     if (F.mode == FIN_EM && *F.stopped) return;
@@ -3635,11 +3677,18 @@ __global__ __launch_bounds__(kFinThreads) void reduce_cols_kernel(FinArgs F, con
         double u = rsh[t];
 #pragma unroll
         for (int w = 1; w < kFinWaves; ++w) u += rsh[w * kRedCols + t];
-        red[col] = u;
+        __hip_atomic_store(red + col, u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    // The sums are device-scope stores (written through to the device's coherence point, so no
+    // cache write-back is needed); the workgroup counts itself done once they have completed, and
+    // the last one reads them back with device-scope loads.
+    wait_vm<0>();
+    __syncthreads();
+    if (t == 0) last = atomicInc(count, gridDim.x - 1) == gridDim.x - 1;
+    __syncthreads();
+    if (!last) return;
+    finalize_body(F);
 }
-
-__global__ __launch_bounds__(kFinThreads) void finalize_kernel(FinArgs F) { finalize_body(F); }
 
 // ------------------------------------------------------------------------------------------
 // a8: histogram of integer rotation errors (mod L).
@@ -3701,6 +3750,13 @@ hipError_t launch_colsum(const void *obs, int is_c128, int64_t N, int D, double 
     return hipGetLastError();
 }
 
+hipError_t launch_sum(const double *x, int64_t n, double *partials, int G, double *out,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(sum_kernel, dim3(G), dim3(256), 0, s, x, n, partials);
+    hipLaunchKernelGGL(sum_kernel2, dim3(1), dim3(64), 0, s, partials, G, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_reduce(const double *partials, int G, int ncols, double *out, hipStream_t s) {
     hipLaunchKernelGGL(reduce_kernel, dim3((ncols + 63) / 64), dim3(512), 0, s, partials, G,
                        ncols, out);
@@ -3733,10 +3789,9 @@ hipError_t launch_template(const TplArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_reduce_finalize(const FinArgs &a, const double *partials, int G, int ncols,
-                                  double *red, hipStream_t s) {
-    hipLaunchKernelGGL(reduce_cols_kernel, dim3((ncols + kRedCols - 1) / kRedCols),
-                       dim3(kFinThreads), 0, s, a, partials, G, ncols, red);
-    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kFinThreads), 0, s, a);
+                                  double *red, unsigned *count, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_finalize_kernel, dim3((ncols + kRedCols - 1) / kRedCols),
+                       dim3(kFinThreads), 0, s, a, partials, G, ncols, red, count);
     return hipGetLastError();
 }
 hipError_t launch_histogram(const int32_t *err, int64_t n, int L, unsigned long long *counts,

@@ -51,7 +51,11 @@ def test_adjoint_matches_oracle_fisher_gradient(gpu, prec, tol, W):
 
 
 def test_adjoint_against_gpu_finite_differences(gpu):
-    """FP64: central differences of the GPU log-likelihood itself against the GPU adjoint."""
+    """FP64: fourth-order central differences of the GPU log-likelihood itself against the GPU
+    adjoint.  A difference quotient with step h carries the log-likelihood's rounding error delta
+    amplified to about 1.5 delta / h; delta is taken as 64 ulps of |LL| (the FP64 sums of the pass
+    and the finalize, with cancellation among terms a few times |LL|), and h = 1e-4 of each
+    argument's scale keeps the h^4 truncation term far below that floor."""
     import torch
     from paper_2105_07372_amd import EM
     w, V, lo, eta, a, s2 = _fd_problem(7)
@@ -59,26 +63,34 @@ def test_adjoint_against_gpu_finite_differences(gpu):
             precision="fp64")
     ll = lambda a_, s_, e_: em.loglik_fwd(torch.from_numpy(a_).to(gpu), s_,
                                           torch.from_numpy(e_).to(gpu))
-    ll(a, s2, eta)
+    ll0 = ll(a, s2, eta)
     ga = torch.empty(w.D, dtype=torch.complex128, device=gpu)
     ge = torch.empty(7, dtype=torch.float64, device=gpu)
     gs = em.loglik_bwd(1.0, ga, ge)
     ga, ge = ga.cpu().numpy(), ge.cpu().numpy()
-    h = 1e-6 * float(np.abs(a).max())
+    delta = 64 * np.finfo(np.float64).eps * abs(ll0)
+
+    def fd4(f, h):
+        return (8 * (f(h) - f(-h)) - (f(2 * h) - f(-2 * h))) / (12 * h)
+
+    def bar(h, g):
+        return 1.5 * delta / h + 1e-9 * max(1.0, abs(g))
+
+    h = 1e-4 * float(np.abs(a).max())
     for d in range(0, w.D, 5):
         for unit, comp in ((1.0, ga[d].real), (1j, ga[d].imag)):
             e = np.zeros(w.D, complex)
-            e[d] = unit * h
-            fd = (ll(a + e, s2, eta) - ll(a - e, s2, eta)) / (2 * h)
-            assert abs(fd - comp) <= 1e-6 * max(1.0, abs(comp))
-    hs = 1e-6 * s2
-    fd = (ll(a, s2 + hs, eta) - ll(a, s2 - hs, eta)) / (2 * hs)
-    assert abs(fd - gs) <= 1e-6 * max(1.0, abs(gs))
+            e[d] = unit
+            fd = fd4(lambda x: ll(a + x * e, s2, eta), h)
+            assert abs(fd - comp) <= bar(h, comp), (d, unit, fd, comp)
+    hs = 1e-4 * s2
+    fd = fd4(lambda x: ll(a, s2 + x, eta), hs)
+    assert abs(fd - gs) <= bar(hs, gs), (fd, gs)
     for i in range(7):
         e = np.zeros(7)
-        e[i] = 1e-6
-        fd = (ll(a, s2, eta + e) - ll(a, s2, eta - e)) / 2e-6
-        assert abs(fd - ge[i]) <= 1e-5 * max(1.0, abs(ge[i]))
+        e[i] = 1.0
+        fd = fd4(lambda x: ll(a, s2, eta + x * e), 1e-4)
+        assert abs(fd - ge[i]) <= bar(1e-4, ge[i]), (i, fd, ge[i])
     em.close()
 
 
