@@ -256,7 +256,9 @@ em_status em_set_stream(em_ctx *ctx, void *stream);
 em_status em_pass_time(em_ctx *ctx, double *ms_total, int64_t *launches, int32_t reset);
 
 /* Launch geometry and storage of the context (for reports): rows per tile, workgroups of the E+M
- * pass, bytes of observation storage per row, padded window, name of the E+M kernel variant. */
+ * pass, bytes of observation storage per row, padded window, name of the E+M kernel variant that
+ * em_step runs (posterior queries and the adjoint's passes of a factored context over a window
+ * symmetric about 0 run the plain factored variant). */
 typedef struct {
     int32_t rows_per_tile, grid, threads, window_padded;
     int64_t bytes_per_row;

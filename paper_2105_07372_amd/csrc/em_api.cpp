@@ -43,6 +43,9 @@ struct em_ctx {
     bool wide = false;    // wide-row pass (rows streamed through an LDS ring, 128-row tiles)
     int wNTW = 0, wUR = 0;
     bool fac = false;     // factored pass (per-frequency sums; no template)
+    bool fs = false;      // ... and its symmetric-window form for the EM and log-likelihood passes
+    int fsMTW = 0;
+    size_t fsLds = 0;
     bool kr = false;      // row-stream correlation pass (template in registers, rows via LDS)
     int krNT = 0;
     bool gm = false;      // long-window FP32 pass (GEMM with a posterior / M-step epilogue)
@@ -155,6 +158,7 @@ em_status plan(em_ctx *c, size_t lds_max) {
     c->ks = false;
     c->wide = false;
     c->fac = false;
+    c->fs = false;
     c->kr = false;
     c->gm = false;
     if (c->flags & EM_FLAG_FACTORED) {
@@ -170,6 +174,14 @@ em_status plan(em_ctx *c, size_t lds_max) {
             c->fEPL = EPL;
             c->WM = 0;
             c->lds = lds;
+            int MTW = 0;
+            size_t fl = 0;
+            if (fs_plan(c->prec, c->D, c->Q, c->K, c->L, c->lo, c->W, c->Wp, !c->has_angles,
+                        lds_max, &MTW, &fl)) {
+                c->fs = true;
+                c->fsMTW = MTW;
+                c->fsLds = fl;
+            }
             return EM_OK;
         }
         return fail(c, EM_EUNSUPPORTED,
@@ -390,6 +402,8 @@ em_status run_pass(em_ctx *c, int flags, int64_t r0, int64_t r1, const double *a
         HIPCHK(c, launch_pass_ks(c->prec, c->BM, c->ksNT, c->ksKSS, A, grid, c->lds, c->stream));
     else if (c->wide)
         HIPCHK(c, launch_pass_wide(c->prec, c->wNTW, c->wUR, A, grid, c->lds, c->stream));
+    else if (c->fs && !(flags & (PF_QUERY | PF_STORE_LSE | PF_LOAD_LSE)))
+        HIPCHK(c, launch_pass_fs(c->prec, c->fsMTW, A, grid, c->fsLds, c->stream));
     else if (c->fac)
         HIPCHK(c, launch_pass_fac(c->prec, c->fWIDE, c->fKCM, c->fEPL, A, grid, c->lds, c->stream));
     else
@@ -558,6 +572,14 @@ em_status em_init(em_ctx **out, const em_params *p, const void *obs_dev, const d
         if (pass_fac_setup(c->prec, c->fWIDE, c->fKCM, c->fEPL, c->lds, &occ) != hipSuccess || occ < 1) {
             (void)hipGetLastError();
             occ = 1;
+        }
+        int occ_fs = 1;
+        if (c->fs) {   // both kernels fill the same partial rows: the smaller resident grid
+            if (pass_fs_setup(c->prec, c->fsMTW, c->fsLds, &occ_fs) != hipSuccess || occ_fs < 1) {
+                (void)hipGetLastError();
+                occ_fs = 1;
+            }
+            if (occ_fs < occ) occ = occ_fs;
         }
     } else {
         if (pass_setup(c->prec, c->BM, c->WM, c->LD, c->lds, &occ) != hipSuccess || occ < 1) {
@@ -1176,9 +1198,10 @@ em_status em_get_info(const em_ctx *c, em_info *info) {
     info->threads = kThreads;
     info->window_padded = c->Wp;
     info->bytes_per_row = c->rowbytes;
-    info->lds_bytes = (int64_t)c->lds;
+    info->lds_bytes = (int64_t)(c->fs ? c->fsLds : c->lds);
     std::snprintf(info->kernel, sizeof info->kernel, "%s",
-                  c->kr     ? pass_kr_name(c->prec, c->krNT)
+                  c->fs     ? pass_fs_name(c->prec, c->fsMTW)
+                  : c->kr   ? pass_kr_name(c->prec, c->krNT)
                   : c->gm   ? pass_gm_name(c->gmNT)
                   : c->ks   ? pass_ks_name(c->prec, c->BM, c->ksNT, c->ksKSS)
                   : c->wide ? pass_wide_name(c->prec, c->wNTW, c->wUR)

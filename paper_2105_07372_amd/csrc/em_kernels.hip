@@ -3381,6 +3381,413 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
 }
 
 // ------------------------------------------------------------------------------------------
+// Factored E(+M) pass over a window that is symmetric about offset 0 (the full search on the
+// grid, or offsets -h .. h): the offsets +m and -m share the cosines of the rotation phases and
+// have sines of opposite sign, so with
+//   P_j(m) = sum_k Re c_jk cos(kbar_k theta_m),    Q_j(m) = sum_k Im c_jk sin(kbar_k theta_m)
+// the correlations are C_j(+m) = P_j(m) + Q_j(m) and C_j(-m) = P_j(m) - Q_j(m), and
+//   Re U_jk = sum_m (w_j(+m) + w_j(-m)) cos(kbar_k theta_m),
+//   Im U_jk = sum_m (w_j(+m) - w_j(-m)) sin(kbar_k theta_m)
+// (an offset that is its own mirror, 0 or L/2, enters once, with its sines set to 0).  This is the
+// factored rewrite of §I eq. (3) with half of its matrix-core products.  Layout: 16-row tiles, two
+// rows per wave held in registers (lane l: entries 8 l .. 8 l + 7, D = 512), the next tile's rows
+// loading meanwhile; c_jk (scaled by coef s_j) staged in LDS as B fragments; the half-window
+// m = 0 .. M - 1 in 16-offset tiles dealt to the waves in turn (wave w: tiles w and w + 8, so
+// each SIMD gets the same number), the cosine and sine tables in LDS in A-fragment order.  The
+// products run with the window on the matrix rows (C^T = E^T c^T), so each lane holds its row
+// j = lane % 16 at four window offsets per tile, and the same registers are the B operand of
+// U^T = E w^T (window index 16 t + 4 g + q of lane group g at k-step (t, q)).  Row maxima and sums
+// are combined over the waves through LDS in wave order; U^T partials per wave go through LDS and
+// are added in wave order by the M-step.  No posterior queries or stored log-sum-exps: those
+// passes take the plain factored kernel.
+
+constexpr int kFsKS = 8;          // k-steps of 4 over K <= 32
+constexpr int kFsCW = 36;         // stride (floats) of a staged c row: [q][ks] order, padded
+constexpr int kFsWFlush = 16;     // tiles of FP32 W_t partials per FP64 flush
+
+struct FsLds {
+    int off_ct, off_st, off_lr, off_c, off_x, off_u, off_sw, off_w, off_a, total;
+};
+__host__ __device__ inline FsLds fs_lds(int MT, int D, int Wp) {
+    FsLds l;
+    l.off_ct = 0;                                          // cos table, MT x kFsKS x 64
+    l.off_st = l.off_ct + MT * kFsKS * 64 * 4;             // sin table
+    l.off_lr = l.off_st + MT * kFsKS * 64 * 4;             // log rho at +m, then at -m
+    l.off_c = l.off_lr + 2 * MT * 16 * 4;                  // Re c rows, then Im c rows
+    l.off_x = l.off_c + 2 * 16 * kFsCW * 4;                // (max, sum) per wave and row
+    l.off_u = l.off_x + 8 * 16 * 8;                        // U^T partials: [wave][row][k] float2
+    l.off_sw = l.off_u + 8 * 16 * 32 * 8;                  // M-step partials per wave
+    l.off_w = align_up(l.off_sw + 8 * (9 * D / 8) * 8, 16);  // W_t (FP64)
+    l.off_a = align_up(l.off_w + Wp * 8, 16);              // a (FP32), lane-major
+    l.total = l.off_a + D * 8;
+    return l;
+}
+
+// The half window (lo taken mod L): W = L (the full search, any lo) or W = 2 h + 1 with
+// lo = -h mod L (offsets -h .. h).  M offsets m = 0 .. M - 1; fs_plus(m) is the window index of
+// offset +m, fs_mirror(m) that of -m, or -1 when -m is +m itself (m = 0, or L / 2 for even L).
+__host__ __device__ inline int fs_halves(int L, int lo, int W) {
+    return W == L ? L / 2 + 1 : (W + 1) / 2;
+}
+__host__ __device__ inline int fs_mod(int x, int L) {
+    const int r = x % L;
+    return r < 0 ? r + L : r;
+}
+__host__ __device__ inline int fs_plus(int m, int L, int lo) { return fs_mod(m - lo, L); }
+__host__ __device__ inline int fs_mirror(int m, int L, int lo, int W) {
+    const int i = fs_mod(-m - lo, L);
+    return (i < W && i != fs_plus(m, L, lo)) ? i : -1;
+}
+
+template <int P, int MTW>
+__global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
+    constexpr int EPL = 8, RPW = 2, BM = 16;
+    if ((A.flags & PF_CHECK_STOP) && *A.stopped) return;
+
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int g = lane >> 4, c16 = lane & 15;
+    const int K = A.K, D = A.D, L = A.L, lo = A.lo, W = A.W, Wp = A.Wp;
+    const int M = fs_halves(L, lo, W), MT = (M + 15) / 16;
+    const FsLds LY = fs_lds(MT, D, Wp);
+    float *ct = (float *)(smem + LY.off_ct);
+    float *st = (float *)(smem + LY.off_st);
+    float *lrp = (float *)(smem + LY.off_lr);
+    float *lrm = lrp + MT * 16;
+    float *cs = (float *)(smem + LY.off_c);
+    float2 *xs = (float2 *)(smem + LY.off_x);
+    float2 *up = (float2 *)(smem + LY.off_u);
+    float2 *Sw = (float2 *)(smem + LY.off_sw);
+    double *wt64 = (double *)(smem + LY.off_w);
+    float2 *as = (float2 *)(smem + LY.off_a);
+
+    // tables: ct / st entry (t, s, l) = cos / sin (kbar_k theta_m) at m = 16 t + l % 16,
+    // k = 4 s + l / 16 (zero past M and K; sines zero where the offset is its own mirror)
+    for (int x = tid; x < MT * kFsKS * 64; x += kThreads) {
+        const int ln = x & 63, ks = (x >> 6) % kFsKS, mt = x / (64 * kFsKS);
+        const int m = 16 * mt + (ln & 15), k = 4 * ks + (ln >> 4);
+        float cv = 0.f, sv = 0.f;
+        if (m < M && k < K) {
+            const float *e = A.E2 + (int64_t)fs_plus(m, L, lo) * 2 * K;
+            cv = e[k];
+            sv = fs_mirror(m, L, lo, W) >= 0 ? e[K + k] : 0.f;
+        }
+        ct[x] = cv;
+        st[x] = sv;
+    }
+    for (int m = tid; m < MT * 16; m += kThreads) {
+        float p = -INFINITY, q = -INFINITY;
+        if (m < M) {
+            p = A.logrho32[fs_plus(m, L, lo)];
+            const int im = fs_mirror(m, L, lo, W);
+            if (im >= 0) q = A.logrho32[im];
+        }
+        lrp[m] = p;
+        lrm[m] = q;
+    }
+    for (int x = tid; x < 2 * 16 * kFsCW; x += kThreads) cs[x] = 0.f;   // k >= K stays zero
+    // the exchange slots of waves without window tiles keep (-inf, 0) and zero U partials
+    for (int x = tid; x < 8 * 16; x += kThreads) xs[x] = make_float2(-INFINITY, 0.f);
+    for (int x = tid; x < 8 * 16 * 32; x += kThreads) up[x] = make_float2(0.f, 0.f);
+    for (int i = tid; i < Wp; i += kThreads) wt64[i] = 0.0;
+    for (int d = tid; d < D; d += kThreads)
+        as[(d % EPL) * 64 + d / EPL] = make_float2((float)A.a[2 * d], (float)A.a[2 * d + 1]);
+    __syncthreads();
+
+    const int kl = EPL * lane / A.Q;               // this lane's angular frequency index
+    const int LPK = A.Q / EPL;
+    float lpk_f[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) lpk_f[t] = LPK > (1 << t) ? 1.f : 0.f;
+    float2 areg[EPL];
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) areg[e] = as[e * 64 + lane];
+    const float coef = (float)A.coef;
+    const int nwu = MT < 8 ? MT : 8;                // waves holding window tiles
+
+    PassAcc<1> acc;
+    acc.init();
+    const int64_t ntiles = (A.row_end - A.row_begin + BM - 1) / BM;
+    FacRow<P, EPL> vn[RPW];
+    float rsn[RPW];
+    auto load_tile = [&](int64_t t) {
+        const int64_t rb = A.row_begin + t * BM + RPW * wave;
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+            const int64_t row = rb + r < A.row_end ? rb + r : A.row_end - 1;
+            vn[r].load(A.V + row * A.rowbytes, A.Dp, lane);
+            rsn[r] = A.rowscale ? A.rowscale[row] : 1.0f;
+        }
+    };
+    float sr[EPL], si[EPL];
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) sr[e] = si[e] = 0.f;
+    int nacc = 0;
+    auto flush_s = [&]() {
+        // wave w's partials at [w][9 (d / 8) + d % 8], then summed in wave order per entry
+        const int SWS = 9 * D / 8;
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) Sw[wave * SWS + 9 * lane + e] = make_float2(sr[e], si[e]);
+        lds_barrier();
+        const int d = tid;
+        if (d < D) {
+            const int o = 9 * (d >> 3) + (d & 7);
+            float2 s = Sw[o];
+#pragma unroll
+            for (int w = 1; w < 8; ++w) {
+                const float2 t = Sw[w * SWS + o];
+                s.x += t.x;
+                s.y += t.y;
+            }
+            acc.S[0].x += (double)s.x;
+            acc.S[0].y += (double)s.y;
+        }
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) sr[e] = si[e] = 0.f;
+        nacc = 0;
+    };
+    // this lane's W_t partials (its row j = c16, its window offsets), FP32 over kFsWFlush tiles;
+    // the flush sums the 16 rows by DPP and adds them in FP64 (each offset has one owner lane)
+    float wsp[MTW][4], wsm[MTW][4];
+#pragma unroll
+    for (int t = 0; t < MTW; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) wsp[t][q] = wsm[t][q] = 0.f;
+    int nw = 0;
+    auto flush_w = [&]() {
+#pragma unroll
+        for (int t = 0; t < MTW; ++t) {
+            const int mt = wave + 8 * t;
+            if (mt >= MT) break;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float sp = row16_sum(wsp[t][q]), sm = row16_sum(wsm[t][q]);
+                const int m = 16 * mt + 4 * g + q;
+                if (c16 == 0 && m < M) {
+                    wt64[fs_plus(m, L, lo)] += (double)sp;
+                    const int im = fs_mirror(m, L, lo, W);
+                    if (im >= 0) wt64[im] += (double)sm;
+                }
+                wsp[t][q] = wsm[t][q] = 0.f;
+            }
+        }
+        nw = 0;
+    };
+    double wc_acc = 0.0;
+
+    int64_t tile = blockIdx.x;
+    if (tile < ntiles) load_tile(tile);
+    for (; tile < ntiles; tile += gridDim.x) {
+        const int64_t r0 = A.row_begin + tile * BM;
+        const int rows = (int)((A.row_end - r0) < BM ? (A.row_end - r0) : BM);
+        FacRow<P, EPL> vc[RPW];
+        float rsc[RPW];
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+            vc[r] = vn[r];
+            rsc[r] = rsn[r];
+        }
+        const bool pf = tile + gridDim.x < ntiles;
+        if (pf && wave < 4) load_tile(tile + gridDim.x);
+
+        // ---- c_jk of this wave's rows, scaled by coef s_j, into the B-fragment staging
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+            const int j = RPW * wave + r;
+            float cr = 0.f, ci = 0.f;
+#pragma unroll
+            for (int e = 0; e < EPL; ++e) {
+                const float2 v = vc[r].entry(e);
+                cr = fmaf(v.x, areg[e].x, cr);            // Re conj(v) a
+                cr = fmaf(v.y, areg[e].y, cr);
+                ci = fmaf(v.x, areg[e].y, ci);            // Im conj(v) a
+                ci = fmaf(-v.y, areg[e].x, ci);
+            }
+            cr = lanes_sum_dpp(cr, lpk_f);
+            ci = lanes_sum_dpp(ci, lpk_f);
+            for (int o = 16; o < LPK; o <<= 1) {
+                cr += __shfl_xor(cr, o);
+                ci += __shfl_xor(ci, o);
+            }
+            const float u = j < rows ? rsc[r] : 1.0f;
+            if ((lane & (LPK - 1)) == 0) {
+                const int o = j * kFsCW + (kl & 3) * 8 + (kl >> 2);
+                cs[o] = cr * (coef * u);
+                cs[16 * kFsCW + o] = ci * (coef * u);
+            }
+        }
+        lds_barrier();
+        if (pf && wave >= 4) load_tile(tile + gridDim.x);
+
+        // ---- P^T and Q^T for this wave's window tiles; log-weights at +m and -m
+        float br[kFsKS], bi[kFsKS];
+        {
+            const float4 *pr = (const float4 *)(cs + c16 * kFsCW + 8 * g);
+            const float4 *pi = (const float4 *)(cs + 16 * kFsCW + c16 * kFsCW + 8 * g);
+            const float4 r0v = pr[0], r1v = pr[1], i0v = pi[0], i1v = pi[1];
+            br[0] = r0v.x; br[1] = r0v.y; br[2] = r0v.z; br[3] = r0v.w;
+            br[4] = r1v.x; br[5] = r1v.y; br[6] = r1v.z; br[7] = r1v.w;
+            bi[0] = i0v.x; bi[1] = i0v.y; bi[2] = i0v.z; bi[3] = i0v.w;
+            bi[4] = i1v.x; bi[5] = i1v.y; bi[6] = i1v.z; bi[7] = i1v.w;
+        }
+        float lp[MTW][4], lm[MTW][4];
+        float mloc = -INFINITY;
+#pragma unroll
+        for (int t = 0; t < MTW; ++t) {
+            const int mt = wave + 8 * t;
+            if (mt >= MT) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) lp[t][q] = lm[t][q] = -INFINITY;
+                continue;
+            }
+            f32x4 pa = (f32x4){0.f, 0.f, 0.f, 0.f}, qa = pa;
+            const float *ca = ct + mt * kFsKS * 64 + lane;
+            const float *sa = st + mt * kFsKS * 64 + lane;
+#pragma unroll
+            for (int ks = 0; ks < kFsKS; ++ks) {
+                pa = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[64 * ks], br[ks], pa, 0, 0, 0);
+                qa = __builtin_amdgcn_mfma_f32_16x16x4f32(sa[64 * ks], bi[ks], qa, 0, 0, 0);
+            }
+            const float4 lp4 = *(const float4 *)(lrp + 16 * mt + 4 * g);
+            const float4 lm4 = *(const float4 *)(lrm + 16 * mt + 4 * g);
+            const float lpv[4] = {lp4.x, lp4.y, lp4.z, lp4.w};
+            const float lmv[4] = {lm4.x, lm4.y, lm4.z, lm4.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                lp[t][q] = (pa[q] + qa[q]) + lpv[q];
+                lm[t][q] = (pa[q] - qa[q]) + lmv[q];
+                mloc = fmaxf(mloc, fmaxf(lp[t][q], lm[t][q]));
+            }
+        }
+        // this wave's maximum and sum for row j over the four lane groups
+        mloc = fmaxf(mloc, swz_xor16(mloc));
+        mloc = fmaxf(mloc, __shfl_xor(mloc, 32));
+        float ep[MTW][4], em[MTW][4], sloc = 0.f;
+#pragma unroll
+        for (int t = 0; t < MTW; ++t)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                ep[t][q] = lp[t][q] == -INFINITY ? 0.f : __expf(lp[t][q] - mloc);
+                em[t][q] = lm[t][q] == -INFINITY ? 0.f : __expf(lm[t][q] - mloc);
+                sloc += ep[t][q] + em[t][q];
+            }
+        sloc += swz_xor16(sloc);
+        sloc += __shfl_xor(sloc, 32);
+        if (g == 0 && wave < nwu) xs[wave * 16 + c16] = make_float2(mloc, sloc);
+        lds_barrier();
+
+        // ---- posteriors: the row's maximum and sum over the waves, in wave order
+        float2 xw[8];
+#pragma unroll
+        for (int w = 0; w < 8; ++w) xw[w] = xs[w * 16 + c16];
+        float gmax = xw[0].x;
+#pragma unroll
+        for (int w = 1; w < 8; ++w) gmax = fmaxf(gmax, xw[w].x);
+        float tot = 0.f;
+#pragma unroll
+        for (int w = 0; w < 8; ++w) tot += xw[w].y > 0.f ? xw[w].y * __expf(xw[w].x - gmax) : 0.f;
+        const bool valid = c16 < rows;
+        const float scale = (valid && sloc > 0.f) ? __expf(mloc - gmax) / tot : 0.f;
+        float wcl = 0.f;
+#pragma unroll
+        for (int t = 0; t < MTW; ++t) {
+            const int mt = wave + 8 * t;
+            if (mt >= MT) break;
+            const float4 lp4 = *(const float4 *)(lrp + 16 * mt + 4 * g);
+            const float4 lm4 = *(const float4 *)(lrm + 16 * mt + 4 * g);
+            const float lpv[4] = {lp4.x, lp4.y, lp4.z, lp4.w};
+            const float lmv[4] = {lm4.x, lm4.y, lm4.z, lm4.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                ep[t][q] *= scale;
+                em[t][q] *= scale;
+                if (ep[t][q] > 0.f) wcl = fmaf(ep[t][q], lp[t][q] - lpv[q], wcl);
+                if (em[t][q] > 0.f) wcl = fmaf(em[t][q], lm[t][q] - lmv[q], wcl);
+                wsp[t][q] += ep[t][q];
+                wsm[t][q] += em[t][q];
+            }
+        }
+        wc_acc += (double)wcl;                    // sum_i w_ji (l_ji - log rho_i), this lane's
+        if (wave == 0 && g == 0 && valid) {
+            acc.lse += (double)(gmax + __logf(tot));
+            acc.rows += 1.0;
+        }
+        if (++nw == kFsWFlush) flush_w();
+        if (!(A.flags & PF_ACC_M)) continue;
+
+        // ---- U^T = E w^T over this wave's window tiles (Re: cos with w(+m) + w(-m); Im: sin
+        // with w(+m) - w(-m)); A fragments read from the tables at k = 16 kt + lane % 16
+        f32x4 ur[2], ui[2];
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt) ur[kt] = ui[kt] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < MTW; ++t) {
+            const int mt = wave + 8 * t;
+            if (mt >= MT) break;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float ws = ep[t][q] + em[t][q], wd = ep[t][q] - em[t][q];
+#pragma unroll
+                for (int kt = 0; kt < 2; ++kt) {
+                    const int k = 16 * kt + c16;
+                    const int o = mt * kFsKS * 64 + (k >> 2) * 64 + 4 * g + q + 16 * (k & 3);
+                    ur[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ct[o], ws, ur[kt], 0, 0, 0);
+                    ui[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(st[o], wd, ui[kt], 0, 0, 0);
+                }
+            }
+        }
+        if (wave < nwu) {
+#pragma unroll
+            for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    up[(wave * 16 + c16) * 32 + 16 * kt + 4 * g + q] =
+                        make_float2(ur[kt][q], ui[kt][q]);
+        }
+        lds_barrier();
+
+        // ---- M-step from the rows in registers: U_jk summed over the waves in wave order, times
+        // the row scale; this lane's entries over this wave's rows, FP32 over kFacFlush tiles
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+            const int j = RPW * wave + r;
+            float2 u = make_float2(0.f, 0.f);
+            if (j < rows) {
+                float2 ut[8];
+#pragma unroll
+                for (int w = 0; w < 8; ++w) ut[w] = up[(w * 16 + j) * 32 + kl];
+#pragma unroll
+                for (int w = 0; w < 8; ++w) {
+                    u.x += ut[w].x;
+                    u.y += ut[w].y;
+                }
+                u.x *= rsc[r];
+                u.y *= rsc[r];
+            }
+#pragma unroll
+            for (int e = 0; e < EPL; ++e) {
+                const float2 v = vc[r].entry(e);
+                sr[e] = fmaf(u.x, v.x, sr[e]);            // Re (U v)
+                sr[e] = fmaf(-u.y, v.y, sr[e]);
+                si[e] = fmaf(u.x, v.y, si[e]);            // Im (U v)
+                si[e] = fmaf(u.y, v.x, si[e]);
+            }
+        }
+        if (++nacc == kFacFlush || tile + gridDim.x >= ntiles) flush_s();
+    }
+    if (nw) flush_w();
+    __syncthreads();
+    acc.wc = wc_acc;
+    for (int c = 0; c < 2; ++c) {
+        const int i = tid + c * kThreads;
+        if (i < Wp) acc.W[c] = i < W ? wt64[i] : 0.0;
+    }
+    __syncthreads();
+    if (A.partials) write_partials(A, acc, smem);
+}
+
+// ------------------------------------------------------------------------------------------
 // a6: FP64 reduction of the workgroup partials (kRedCols columns per workgroup, all G rows in a
 // fixed order), then the FP64 finalize in the workgroup that finishes last (one launch).
 
@@ -4138,6 +4545,61 @@ const char *pass_fac_name(int prec, int WIDE, int KCM, int EPL) {
     static thread_local char buf[64];   // (per thread: callers copy it out)
     snprintf(buf, sizeof buf, "pass_fac_kernel<%s,BM=%d,%s,KC=%d%s>", kPrecName[prec],
              fac_bm(prec, EPL), WIDE ? "L2" : "reg", KCM, EPL == 16 ? ",E16" : "");
+    return buf;
+}
+
+
+// Symmetric-window factored pass variants: (precision, window tiles per wave).
+#define SEM_FS_VARIANTS(X)                                                                     \
+    X(P_F32, 1) X(P_F32, 2) X(P_BF16X3, 1) X(P_BF16X3, 2) X(P_F16, 1) X(P_F16, 2)              \
+    X(P_BF16, 1) X(P_BF16, 2)
+
+static pass_fn find_fs(int prec, int MTW) {
+#define SEM_X(P, T)                                                                            \
+    if (prec == P && MTW == T) return pass_fs_kernel<P, T>;
+    SEM_FS_VARIANTS(SEM_X)
+#undef SEM_X
+    return nullptr;
+}
+
+bool fs_plan(int prec, int D, int Q, int K, int L, int lo, int W, int Wp, bool grid,
+             size_t lds_max, int *MTW, size_t *lds) {
+    if (!grid || D != 512 || Q % 8 != 0 || K > 32 || Wp <= 64) return false;
+    const int lpk = Q / 8;
+    if (lpk & (lpk - 1)) return false;                       // lanes per frequency: 2^n
+    if (W != L && !(W % 2 == 1 && fs_mod(lo + (W - 1) / 2, L) == 0))
+        return false;                                        // not symmetric about offset 0
+    const int MT = (fs_halves(L, lo, W) + 15) / 16;
+    const int mtw = (MT + 7) / 8;
+    if (mtw > 2 || !find_fs(prec, mtw)) return false;
+    const size_t b = (size_t)fs_lds(MT, D, Wp).total;
+    if (b > lds_max) return false;
+    *MTW = mtw;
+    *lds = b;
+    return true;
+}
+
+hipError_t launch_pass_fs(int prec, int MTW, const PassArgs &a, int grid, size_t lds,
+                          hipStream_t s) {
+    pass_fn f = find_fs(prec, MTW);
+    if (!f) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(f, dim3(grid), dim3(kThreads), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t pass_fs_setup(int prec, int MTW, size_t lds, int *blocks_per_cu) {
+    pass_fn f = find_fs(prec, MTW);
+    if (!f) return hipErrorInvalidValue;
+    hipError_t e = hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) (void)hipGetLastError();
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void *)f, kThreads,
+                                                        lds);
+}
+
+const char *pass_fs_name(int prec, int MTW) {
+    static thread_local char buf[64];   // (per thread: callers copy it out)
+    snprintf(buf, sizeof buf, "pass_fs_kernel<%s,BM=16,MTW=%d>", kPrecName[prec], MTW);
     return buf;
 }
 

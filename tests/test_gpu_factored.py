@@ -22,7 +22,13 @@ SHAPES = {
     "win128": (4, 128, 72, 6, 1001),       # 16 lanes per frequency: every DPP step of the sum
     "win256": (2, 256, 72, 6, 517),        # 32 lanes per frequency: DPP steps and a shuffle
     "full": (32, 16, 60, None, 2050),      # full search, W = 60
+    # windows symmetric about 0 past 64 offsets: EM and log-likelihood passes take the
+    # symmetric-window kernel (posterior queries the plain one)
+    "full360": (32, 16, 360, None, 3001),  # full search, 181 half-window offsets: 12 tiles
+    "fullodd": (32, 16, 75, None, 1001),   # odd L: no offset at L / 2
+    "win64": (8, 64, 360, 60, 517),        # W = 121, eight lanes per frequency, 2K = 16
 }
+FS_SHAPES = {"win32", "full360", "fullodd", "win64"}
 
 
 def _problem(shape, seed=0):
@@ -54,7 +60,8 @@ def test_factored_teacher_forced_step(gpu, prec, shape):
     print(f"factored shape={shape} prec={prec} N={w.N} W={W}", flush=True)
     em = EM(torch.from_numpy(V.astype(np.complex64)).to(gpu), K=w.K, Q=w.Q, L=w.L, sigma2=s2,
             window=(lo, W), prior=rb, gamma=gamma, precision=prec, factored=True)
-    assert em.info()["kernel"].startswith("pass_fac_kernel"), em.info()
+    want = "pass_fs_kernel" if shape in FS_SHAPES else "pass_fac_kernel"
+    assert em.info()["kernel"].startswith(want), em.info()
     em.set_state(a_t, rho_t, 0)
     offs = oracle.offsets(lo, W)
     wg, am, mg = em.posterior()
@@ -75,6 +82,58 @@ def test_factored_teacher_forced_step(gpu, prec, shape):
     a1, rho1, _ = em.state()
     assert np.linalg.norm(a1 - it["a"]) / np.linalg.norm(it["a"]) <= TOL[prec]["a"]
     assert np.abs(rho1 - it["rho"]).max() <= TOL[prec]["a"]
+    em.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+@pytest.mark.parametrize("case", ["full_lo_neg", "full_lo_pos", "zero_bins", "gamma0"])
+def test_symmetric_window_pass(gpu, prec, case):
+    """The symmetric-window factored kernel on the cases its index maps must get right: a full
+    search that starts at another offset (the window index of +m and -m wraps), a learned prior
+    with empty bins at +m only, at -m only and at 0, and gamma = 0.  Log-likelihood and one step
+    against the oracle; three more steps against the oracle's trajectory."""
+    import torch
+    from paper_2105_07372_amd import EM
+    L = 120
+    w = wl.WORKLOADS["c3"].replace(N=2001, K=32, Q=16, L=L, half_window=45)
+    a_true = wl.image(w, 3)
+    V = wl.observations(w, 3, a=a_true)
+    s2 = wl.noise_variance(a_true, w.snr)
+    if case == "full_lo_neg":
+        lo, W = -L // 2, L
+    elif case == "full_lo_pos":
+        lo, W = 7, L
+    else:
+        lo, W = w.window
+    if W == L:
+        rb = np.full(W, 1.0 / W)
+        gamma = 0.0
+    else:
+        rb, _, _ = oracle.histogram_prior(wl.prior_error_draws(w, 3, 200_000), L, lo, W)
+        gamma = 0.0 if case == "gamma0" else 30.0
+    if case == "zero_bins":
+        h = -lo
+        rb[[h + 3, h - 7, h, 0, W - 1]] = 0.0        # +3, -7, 0 and both window edges
+        rb /= rb.sum()
+    print(f"symmetric window {case} {prec} lo={lo} W={W}", flush=True)
+    em = EM(torch.from_numpy(V.astype(np.complex64)).to(gpu), K=w.K, Q=w.Q, L=L, sigma2=s2,
+            window=(lo, W), prior=rb, gamma=gamma, precision=prec, factored=True)
+    assert em.info()["kernel"].startswith("pass_fs_kernel"), em.info()
+    offs = oracle.offsets(lo, W)
+    a0 = V.astype(np.complex64).astype(np.complex128).mean(axis=0)
+    ll_ref = oracle.loglik(V, a0, rb, s2, w.kbar, L, offs)
+    assert abs(em.loglik() - ll_ref) <= TOL[prec]["ll"] * abs(ll_ref)
+    a_o, rho_o = a0, rb
+    for t in range(4):
+        ref = oracle.em_iteration(V, a_o, rho_o, s2, w.kbar, L, offs, rho_bar=rb, gamma=gamma)
+        em.step(1)
+        a, rho, _ = em.state()
+        assert np.linalg.norm(a - ref["a"]) / np.linalg.norm(ref["a"]) <= 3 * TOL[prec]["a"], t
+        assert np.abs(rho - ref["rho"]).max() <= 3 * TOL[prec]["a"], t
+        assert abs(em.stats()[-1, 1] - ref["ll"]) <= TOL[prec]["ll"] * abs(ref["ll"]), t
+        if case == "zero_bins":
+            assert np.all(rho[rb == 0.0] == 0.0)
+        a_o, rho_o = ref["a"], ref["rho"]
     em.close()
 
 
