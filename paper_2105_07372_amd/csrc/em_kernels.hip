@@ -3402,21 +3402,25 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
 // passes take the plain factored kernel.
 
 constexpr int kFsKS = 8;          // k-steps of 4 over K <= 32
+constexpr int kFsTS = 36;         // stride (floats) of an offset's row of the cosine / sine table:
+                                  // both products' fragment reads fall in distinct banks
 constexpr int kFsCW = 36;         // stride (floats) of a staged c row: [q][ks] order, padded
 constexpr int kFsWFlush = 16;     // tiles of FP32 W_t partials per FP64 flush
+constexpr int kFsUS = 17;         // stride (float2) of a k row of the U^T partials: the M-step's
+                                  // reads (32 k per row j) fall in distinct banks
 
 struct FsLds {
     int off_ct, off_st, off_lr, off_c, off_x, off_u, off_sw, off_w, off_a, total;
 };
 __host__ __device__ inline FsLds fs_lds(int MT, int D, int Wp) {
     FsLds l;
-    l.off_ct = 0;                                          // cos table, MT x kFsKS x 64
-    l.off_st = l.off_ct + MT * kFsKS * 64 * 4;             // sin table
-    l.off_lr = l.off_st + MT * kFsKS * 64 * 4;             // log rho at +m, then at -m
+    l.off_ct = 0;                                          // cos table, MT x 16 x kFsTS
+    l.off_st = l.off_ct + MT * 16 * kFsTS * 4;             // sin table
+    l.off_lr = l.off_st + MT * 16 * kFsTS * 4;             // log rho at +m, then at -m
     l.off_c = l.off_lr + 2 * MT * 16 * 4;                  // Re c rows, then Im c rows
     l.off_x = l.off_c + 2 * 16 * kFsCW * 4;                // (max, sum) per wave and row
-    l.off_u = l.off_x + 8 * 16 * 8;                        // U^T partials: [wave][row][k] float2
-    l.off_sw = l.off_u + 8 * 16 * 32 * 8;                  // M-step partials per wave
+    l.off_u = l.off_x + 8 * 16 * 8;                        // U^T partials: [wave][k][row] float2
+    l.off_sw = l.off_u + 8 * 32 * kFsUS * 8;               // M-step partials per wave
     l.off_w = align_up(l.off_sw + 8 * (9 * D / 8) * 8, 16);  // W_t (FP64)
     l.off_a = align_up(l.off_w + Wp * 8, 16);              // a (FP32), lane-major
     l.total = l.off_a + D * 8;
@@ -3462,11 +3466,10 @@ __global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
     double *wt64 = (double *)(smem + LY.off_w);
     float2 *as = (float2 *)(smem + LY.off_a);
 
-    // tables: ct / st entry (t, s, l) = cos / sin (kbar_k theta_m) at m = 16 t + l % 16,
-    // k = 4 s + l / 16 (zero past M and K; sines zero where the offset is its own mirror)
-    for (int x = tid; x < MT * kFsKS * 64; x += kThreads) {
-        const int ln = x & 63, ks = (x >> 6) % kFsKS, mt = x / (64 * kFsKS);
-        const int m = 16 * mt + (ln & 15), k = 4 * ks + (ln >> 4);
+    // tables: ct / st entry [m][k] (row stride kFsTS) = cos / sin (kbar_k theta_m) (zero past M
+    // and K; sines zero where the offset is its own mirror)
+    for (int x = tid; x < MT * 16 * kFsTS; x += kThreads) {
+        const int m = x / kFsTS, k = x % kFsTS;
         float cv = 0.f, sv = 0.f;
         if (m < M && k < K) {
             const float *e = A.E2 + (int64_t)fs_plus(m, L, lo) * 2 * K;
@@ -3489,7 +3492,7 @@ __global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
     for (int x = tid; x < 2 * 16 * kFsCW; x += kThreads) cs[x] = 0.f;   // k >= K stays zero
     // the exchange slots of waves without window tiles keep (-inf, 0) and zero U partials
     for (int x = tid; x < 8 * 16; x += kThreads) xs[x] = make_float2(-INFINITY, 0.f);
-    for (int x = tid; x < 8 * 16 * 32; x += kThreads) up[x] = make_float2(0.f, 0.f);
+    for (int x = tid; x < 8 * 32 * kFsUS; x += kThreads) up[x] = make_float2(0.f, 0.f);
     for (int i = tid; i < Wp; i += kThreads) wt64[i] = 0.0;
     for (int d = tid; d < D; d += kThreads)
         as[(d % EPL) * 64 + d / EPL] = make_float2((float)A.a[2 * d], (float)A.a[2 * d + 1]);
@@ -3500,9 +3503,6 @@ __global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
     float lpk_f[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) lpk_f[t] = LPK > (1 << t) ? 1.f : 0.f;
-    float2 areg[EPL];
-#pragma unroll
-    for (int e = 0; e < EPL; ++e) areg[e] = as[e * 64 + lane];
     const float coef = (float)A.coef;
     const int nwu = MT < 8 ? MT : 8;                // waves holding window tiles
 
@@ -3526,12 +3526,12 @@ __global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
     int nacc = 0;
     auto flush_s = [&]() {
         // wave w's partials at [w][9 (d / 8) + d % 8], then summed in wave order per entry
-        const int SWS = 9 * D / 8;
+        constexpr int SWS = 9 * 512 / 8;                   // (D = 512)
 #pragma unroll
         for (int e = 0; e < EPL; ++e) Sw[wave * SWS + 9 * lane + e] = make_float2(sr[e], si[e]);
         lds_barrier();
-        const int d = tid;
-        if (d < D) {
+        {
+            const int d = tid;
             const int o = 9 * (d >> 3) + (d & 7);
             float2 s = Sw[o];
 #pragma unroll
@@ -3591,7 +3591,11 @@ __global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
         const bool pf = tile + gridDim.x < ntiles;
         if (pf && wave < 4) load_tile(tile + gridDim.x);
 
-        // ---- c_jk of this wave's rows, scaled by coef s_j, into the B-fragment staging
+        // ---- c_jk of this wave's rows, scaled by coef s_j, into the B-fragment staging (the
+        // lane's coefficients read from LDS once per tile)
+        float2 areg[EPL];
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) areg[e] = as[e * 64 + lane];
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
             const int j = RPW * wave + r;
@@ -3642,12 +3646,13 @@ __global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
                 continue;
             }
             f32x4 pa = (f32x4){0.f, 0.f, 0.f, 0.f}, qa = pa;
-            const float *ca = ct + mt * kFsKS * 64 + lane;
-            const float *sa = st + mt * kFsKS * 64 + lane;
+            // A fragment of k-step ks: offset m = 16 mt + lane % 16, k = 4 ks + lane / 16
+            const float *ca = ct + (16 * mt + c16) * kFsTS + g;
+            const float *sa = st + (16 * mt + c16) * kFsTS + g;
 #pragma unroll
             for (int ks = 0; ks < kFsKS; ++ks) {
-                pa = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[64 * ks], br[ks], pa, 0, 0, 0);
-                qa = __builtin_amdgcn_mfma_f32_16x16x4f32(sa[64 * ks], bi[ks], qa, 0, 0, 0);
+                pa = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[4 * ks], br[ks], pa, 0, 0, 0);
+                qa = __builtin_amdgcn_mfma_f32_16x16x4f32(sa[4 * ks], bi[ks], qa, 0, 0, 0);
             }
             const float4 lp4 = *(const float4 *)(lrp + 16 * mt + 4 * g);
             const float4 lm4 = *(const float4 *)(lrm + 16 * mt + 4 * g);
@@ -3660,18 +3665,48 @@ __global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
                 mloc = fmaxf(mloc, fmaxf(lp[t][q], lm[t][q]));
             }
         }
-        // this wave's maximum and sum for row j over the four lane groups
+        // this wave's maximum and sum for row j over the four lane groups; its exponentials,
+        // relative to that maximum, are the B operand of the U^T product at once (the row's
+        // factor exp(m_wave - m_row) / sum, a column scale of U^T, is applied after the exchange)
         mloc = fmaxf(mloc, swz_xor16(mloc));
         mloc = fmaxf(mloc, __shfl_xor(mloc, 32));
-        float ep[MTW][4], em[MTW][4], sloc = 0.f;
+        const bool accm = (A.flags & PF_ACC_M) != 0;
+        float ep[MTW][4], em[MTW][4], sloc = 0.f, wcl = 0.f;
+        f32x4 ur[2], ui[2];
 #pragma unroll
-        for (int t = 0; t < MTW; ++t)
+        for (int kt = 0; kt < 2; ++kt) ur[kt] = ui[kt] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < MTW; ++t) {
+            const int mtl = (wave + 8 * t) < MT ? wave + 8 * t : 0;
+            const float4 lp4 = *(const float4 *)(lrp + 16 * mtl + 4 * g);
+            const float4 lm4 = *(const float4 *)(lrm + 16 * mtl + 4 * g);
+            const float lpv[4] = {lp4.x, lp4.y, lp4.z, lp4.w};
+            const float lmv[4] = {lm4.x, lm4.y, lm4.z, lm4.w};
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                ep[t][q] = lp[t][q] == -INFINITY ? 0.f : __expf(lp[t][q] - mloc);
-                em[t][q] = lm[t][q] == -INFINITY ? 0.f : __expf(lm[t][q] - mloc);
+                // (the exponentials and sum_i e_ji (l_ji - log rho_i), both relative to m_wave)
+                const bool fp = lp[t][q] != -INFINITY, fm = lm[t][q] != -INFINITY;
+                ep[t][q] = fp ? __expf(lp[t][q] - mloc) : 0.f;
+                em[t][q] = fm ? __expf(lm[t][q] - mloc) : 0.f;
                 sloc += ep[t][q] + em[t][q];
+                if (fp) wcl = fmaf(ep[t][q], lp[t][q] - lpv[q], wcl);
+                if (fm) wcl = fmaf(em[t][q], lm[t][q] - lmv[q], wcl);
             }
+            // U^T = E e^T over this window tile (Re: cos with e(+m) + e(-m); Im: sin with
+            // e(+m) - e(-m)); A fragment: k = 16 kt + lane % 16, offset m = 16 mt + 4 g + q
+            const int mt = wave + 8 * t;
+            if (!accm || mt >= MT) continue;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float ws = ep[t][q] + em[t][q], wd = ep[t][q] - em[t][q];
+#pragma unroll
+                for (int kt = 0; kt < 2; ++kt) {
+                    const int o = (16 * mt + 4 * g + q) * kFsTS + 16 * kt + c16;
+                    ur[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ct[o], ws, ur[kt], 0, 0, 0);
+                    ui[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(st[o], wd, ui[kt], 0, 0, 0);
+                }
+            }
+        }
         sloc += swz_xor16(sloc);
         sloc += __shfl_xor(sloc, 32);
         if (g == 0 && wave < nwu) xs[wave * 16 + c16] = make_float2(mloc, sloc);
@@ -3689,61 +3724,29 @@ __global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
         for (int w = 0; w < 8; ++w) tot += xw[w].y > 0.f ? xw[w].y * __expf(xw[w].x - gmax) : 0.f;
         const bool valid = c16 < rows;
         const float scale = (valid && sloc > 0.f) ? __expf(mloc - gmax) / tot : 0.f;
-        float wcl = 0.f;
 #pragma unroll
         for (int t = 0; t < MTW; ++t) {
-            const int mt = wave + 8 * t;
-            if (mt >= MT) break;
-            const float4 lp4 = *(const float4 *)(lrp + 16 * mt + 4 * g);
-            const float4 lm4 = *(const float4 *)(lrm + 16 * mt + 4 * g);
-            const float lpv[4] = {lp4.x, lp4.y, lp4.z, lp4.w};
-            const float lmv[4] = {lm4.x, lm4.y, lm4.z, lm4.w};
+            if (wave + 8 * t >= MT) break;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                ep[t][q] *= scale;
-                em[t][q] *= scale;
-                if (ep[t][q] > 0.f) wcl = fmaf(ep[t][q], lp[t][q] - lpv[q], wcl);
-                if (em[t][q] > 0.f) wcl = fmaf(em[t][q], lm[t][q] - lmv[q], wcl);
-                wsp[t][q] += ep[t][q];
-                wsm[t][q] += em[t][q];
+                wsp[t][q] = fmaf(ep[t][q], scale, wsp[t][q]);
+                wsm[t][q] = fmaf(em[t][q], scale, wsm[t][q]);
             }
         }
-        wc_acc += (double)wcl;                    // sum_i w_ji (l_ji - log rho_i), this lane's
+        wc_acc += (double)(wcl * scale);          // sum_i w_ji (l_ji - log rho_i), this lane's
         if (wave == 0 && g == 0 && valid) {
             acc.lse += (double)(gmax + __logf(tot));
             acc.rows += 1.0;
         }
         if (++nw == kFsWFlush) flush_w();
-        if (!(A.flags & PF_ACC_M)) continue;
-
-        // ---- U^T = E w^T over this wave's window tiles (Re: cos with w(+m) + w(-m); Im: sin
-        // with w(+m) - w(-m)); A fragments read from the tables at k = 16 kt + lane % 16
-        f32x4 ur[2], ui[2];
-#pragma unroll
-        for (int kt = 0; kt < 2; ++kt) ur[kt] = ui[kt] = (f32x4){0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int t = 0; t < MTW; ++t) {
-            const int mt = wave + 8 * t;
-            if (mt >= MT) break;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const float ws = ep[t][q] + em[t][q], wd = ep[t][q] - em[t][q];
-#pragma unroll
-                for (int kt = 0; kt < 2; ++kt) {
-                    const int k = 16 * kt + c16;
-                    const int o = mt * kFsKS * 64 + (k >> 2) * 64 + 4 * g + q + 16 * (k & 3);
-                    ur[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ct[o], ws, ur[kt], 0, 0, 0);
-                    ui[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(st[o], wd, ui[kt], 0, 0, 0);
-                }
-            }
-        }
+        if (!accm) continue;
         if (wave < nwu) {
 #pragma unroll
             for (int kt = 0; kt < 2; ++kt)
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    up[(wave * 16 + c16) * 32 + 16 * kt + 4 * g + q] =
-                        make_float2(ur[kt][q], ui[kt][q]);
+                    up[(wave * 32 + 16 * kt + 4 * g + q) * kFsUS + c16] =
+                        make_float2(ur[kt][q] * scale, ui[kt][q] * scale);
         }
         lds_barrier();
 
@@ -3756,7 +3759,7 @@ __global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
             if (j < rows) {
                 float2 ut[8];
 #pragma unroll
-                for (int w = 0; w < 8; ++w) ut[w] = up[(w * 16 + j) * 32 + kl];
+                for (int w = 0; w < 8; ++w) ut[w] = up[(w * 32 + kl) * kFsUS + j];
 #pragma unroll
                 for (int w = 0; w < 8; ++w) {
                     u.x += ut[w].x;
