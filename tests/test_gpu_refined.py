@@ -42,7 +42,7 @@ def _problem(case, seed=0):
     return w, a_true, V, s2, th, rb, fac
 
 
-def _teacher_forced(gpu, case, prec):
+def _teacher_forced(gpu, case, prec, staged=False):
     import torch
     from paper_2105_07372_amd import EM
     w, a_true, V, s2, th, rb, fac = _problem(case)
@@ -55,12 +55,14 @@ def _teacher_forced(gpu, case, prec):
     dt = np.complex128 if prec == "fp64" else np.complex64
     print(f"refined case={case} prec={prec} N={w.N} D={w.D} W={W}", flush=True)
     em = EM(torch.from_numpy(V.astype(dt)).to(gpu), K=w.K, Q=w.Q, L=w.L, sigma2=s2, prior=rb,
-            gamma=gamma, precision=prec, angles=th, factored=fac)
+            gamma=gamma, precision=prec, angles=th, factored=fac, staged_pass=staged)
     kern = em.info()["kernel"]
     if fac:
         assert kern.startswith("pass_fac_kernel"), kern
-    elif case == "ksplit" and prec in ("bf16x3", "fp16", "bf16"):
-        assert kern.startswith("pass_ks_kernel"), kern
+    elif case == "ksplit":
+        want = {"fp32": "pass_gm_kernel", "bf16x3": "pass_ks_kernel",
+                "fp16": "pass_ks_kernel" if staged else "pass_kr_kernel"}[prec]
+        assert kern.startswith(want), kern
     em.set_state(a_t, rho_t, 0)
     ang = oracle.AngleList(th)
     wg, am, mg = em.posterior()
@@ -93,9 +95,12 @@ def test_refined_teacher_forced_general(gpu, case, prec):
     _teacher_forced(gpu, case, prec)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16"])
-def test_refined_teacher_forced_ksplit(gpu, prec):
-    _teacher_forced(gpu, "ksplit", prec)
+@pytest.mark.parametrize("prec,staged", [("fp32", False), ("bf16x3", False), ("fp16", False),
+                                          ("fp16", True)])
+def test_refined_teacher_forced_ksplit(gpu, prec, staged):
+    """The default windowed passes on an angle list: the FP32 matrix-core GEMM, the K-split
+    pass (bf16 hi + lo, and fp16 when asked for), the row-stream pass (fp16)."""
+    _teacher_forced(gpu, "ksplit", prec, staged)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp16"])
