@@ -1956,9 +1956,10 @@ __global__ __launch_bounds__(kThreads) void pass_wide_kernel(PassArgs A) {
 //     template rows of its slice for every window tile in registers (hi + lo, built once per
 //     launch from a_t); per tile it reads its slice of the 16 rows from LDS once (MFMA A
 //     fragments) and keeps it in registers for the M-step.
-//   * The eight partial correlations go to LDS; wave w then sums them in wave order for rows w
-//     and w + 8 (one window column per lane), forms the prior-weighted log-sum-exp and the
-//     posteriors with wave reductions, and writes the posteriors as 16-bit hi + lo planes.
+//   * The eight partial correlations go to LDS; wave w then sums them in wave order for rows
+//     2 w and 2 w + 1 (32 lanes per row, two window columns per lane), forms the prior-weighted
+//     log-sum-exp and the posteriors with 32-lane reductions, and writes the posteriors as 16-bit
+//     hi + lo planes.
 //   * U = w E is formed transposed and per wave, for the angular frequencies of the wave's own
 //     entries only (U^T = E'^T w^T: three 16x16x32 products, E' hi + lo in registers), and left
 //     in a wave-private LDS block; the M-step then runs on the wave's own row fragments, so no
@@ -2115,16 +2116,15 @@ __global__ __launch_bounds__(kThreads) void pass_kr_kernel(PassArgs A) {
         }
     };
 
-    // posterior waves: this lane's four window columns 4 px .. 4 px + 3 (the partial slots of
-    // window tile pnt, lane group pg); the row factor; W_t of the four columns (FP32 over 16
-    // tiles, then added into FP64 sums in LDS that only this thread touches)
-    const int px = lane & 15, pnt = px >> 2, pg = px & 3;
+    // posteriors: every wave takes two rows, 32 lanes per row; this lane's two window columns
+    // 2 px .. 2 px + 1 (half ph of the partial slot of window tile pnt, lane group pg); the row
+    // factor; W_t of the two columns (FP32 over 16 tiles, then added into FP64 sums in LDS that
+    // only this thread touches)
+    const int px = lane & 31, pnt = px >> 3, pg = (px >> 1) & 3, ph = px & 1;
     const float ct = (float)A.coef * tsc;
-    float accW[4] = {0.f, 0.f, 0.f, 0.f};
-    double *wacc = (double *)(smem + LY.off_wacc) + (4 * wave + (lane >> 4)) * 64 + 4 * px;
-    if (wave < 4)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) wacc[q] = 0.0;
+    float accW[2] = {0.f, 0.f};
+    double *wacc = (double *)(smem + LY.off_wacc) + (2 * wave + (lane >> 5)) * 64 + 2 * px;
+    wacc[0] = wacc[1] = 0.0;
     int nfw = 0;
     float sr[KSS][4], si[KSS][4];                // M-step sums of this lane's rows (FP32)
 #pragma unroll
@@ -2206,55 +2206,63 @@ __global__ __launch_bounds__(kThreads) void pass_kr_kernel(PassArgs A) {
             red[(wave * 4 + nt) * kKrRedTile + 17 * g + rl] = c4[nt];
         lds_barrier();
 
-        // ---- a4 (waves 0-3): rows 4 wave .. 4 wave + 3, 16 lanes per row, columns 4 x .. 4 x + 3
-        // per lane (x = lane % 16): the 8 partial sums in wave order, the log-sum-exp by 16-lane
-        // DPP reductions, the posteriors written as 16-bit hi + lo planes
-        if (wave < 4) {
-            const int r = 4 * wave + (lane >> 4);
+        // ---- a4: rows 2 wave, 2 wave + 1, 32 lanes per row, columns 2 x, 2 x + 1 per lane (x =
+        // lane % 32): the 8 partial sums in wave order, the log-sum-exp by 32-lane reductions
+        // (16-lane DPP rows, then the swizzle across the pair of rows), the posteriors written as
+        // 16-bit hi + lo planes
+        {
+            const int r = 2 * wave + (lane >> 5);
             const bool rv = r < rows;
-            float l[4], e[4];
-            const float4 lr4 = *(const float4 *)(lrs + 4 * px);
-            const bool cok[4] = {4 * px < W, 4 * px + 1 < W, 4 * px + 2 < W, 4 * px + 3 < W};
+            float l[2], e[2];
+            const float2 lr2 = *(const float2 *)(lrs + 2 * px);
+            const bool cok[2] = {2 * px < W, 2 * px + 1 < W};
             {
-                f32x4 v = red[(0 * 4 + pnt) * kKrRedTile + 17 * pg + r];
+                const float *rp = (const float *)red + 4 * (pnt * kKrRedTile + 17 * pg + r) + 2 * ph;
+                float2 v = *(const float2 *)rp;
 #pragma unroll
-                for (int w2 = 1; w2 < 8; ++w2) v += red[(w2 * 4 + pnt) * kKrRedTile + 17 * pg + r];
+                for (int w2 = 1; w2 < 8; ++w2) {
+                    const float2 t = *(const float2 *)(rp + 4 * (w2 * 4 * kKrRedTile));
+                    v.x += t.x;
+                    v.y += t.y;
+                }
                 const float rf = ct * rsv[r];
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    l[q] = (rv && cok[q]) ? v[q] * rf + (&lr4.x)[q] : -INFINITY;
+                l[0] = (rv && cok[0]) ? v.x * rf + lr2.x : -INFINITY;
+                l[1] = (rv && cok[1]) ? v.y * rf + lr2.y : -INFINITY;
             }
             float lse;
             if (A.flags & PF_LOAD_LSE) {
                 lse = rv ? (float)A.lse[r0 + r] : 0.f;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) e[q] = __expf(l[q] - lse);
+                for (int q = 0; q < 2; ++q) e[q] = __expf(l[q] - lse);
             } else {
-                float mx = row16_max(fmaxf(fmaxf(l[0], l[1]), fmaxf(l[2], l[3])));
+                float mx = row16_max(fmaxf(l[0], l[1]));
+                mx = fmaxf(mx, swz_xor16(mx));
                 if (!rv) mx = 0.f;                         // (an empty row: every l is -inf)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) e[q] = __expf(l[q] - mx);   // exp(-inf) = 0
-                const float sx = row16_sum((e[0] + e[1]) + (e[2] + e[3]));
+                for (int q = 0; q < 2; ++q) e[q] = __expf(l[q] - mx);   // exp(-inf) = 0
+                float sx = row16_sum(e[0] + e[1]);
+                sx += swz_xor16(sx);
                 lse = mx + __logf(sx);
                 const float is = rv ? __builtin_amdgcn_rcpf(sx) : 0.f;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) e[q] *= is;
+                for (int q = 0; q < 2; ++q) e[q] *= is;
             }
             // e[] are the posteriors; sum_i w_i (l_i - log rho_i) for the per-row sum of w C
-            float wcs = 0.f;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) wcs += e[q] > 0.f ? e[q] * (l[q] - (&lr4.x)[q]) : 0.f;
+            float wcs = (e[0] > 0.f ? e[0] * (l[0] - lr2.x) : 0.f) +
+                        (e[1] > 0.f ? e[1] * (l[1] - lr2.y) : 0.f);
             wcs = row16_sum(wcs);
+            wcs += swz_xor16(wcs);
             {
-                H hv[4], gv[4];
+                H hv[2], gv[2];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < 2; ++q) {
                     hv[q] = (H)e[q];
                     gv[q] = (H)(e[q] - (float)hv[q]);
                     accW[q] += e[q];
                 }
-                *(uint2 *)(wsh + r * kKrWS + 8 * px) = __builtin_bit_cast(uint2, hv);
-                *(uint2 *)(wsh + BM * kKrWS + r * kKrWS + 8 * px) = __builtin_bit_cast(uint2, gv);
+                *(uint32_t *)(wsh + r * kKrWS + 4 * px) = __builtin_bit_cast(uint32_t, hv);
+                *(uint32_t *)(wsh + BM * kKrWS + r * kKrWS + 4 * px) =
+                    __builtin_bit_cast(uint32_t, gv);
             }
             if (rv && px == 0) {
                 acc_lse += (double)lse;
@@ -2264,24 +2272,26 @@ __global__ __launch_bounds__(kThreads) void pass_kr_kernel(PassArgs A) {
             }
             if constexpr (query) {
                 // argmax (lowest column among equal maxima) and the gap to the runner-up
-                const float m1 = row16_max(fmaxf(fmaxf(e[0], e[1]), fmaxf(e[2], e[3])));
+                float m1 = row16_max(fmaxf(e[0], e[1]));
+                m1 = fmaxf(m1, swz_xor16(m1));
                 int idx = 1 << 30;
 #pragma unroll
-                for (int q = 3; q >= 0; --q)
-                    if (cok[q] && e[q] == m1) idx = 4 * px + q;
+                for (int q = 1; q >= 0; --q)
+                    if (cok[q] && e[q] == m1) idx = 2 * px + q;
 #pragma unroll
-                for (int o = 1; o < 16; o <<= 1) idx = min(idx, __shfl_xor(idx, o));
+                for (int o = 1; o < 32; o <<= 1) idx = min(idx, __shfl_xor(idx, o));
                 float m2 = 0.f;
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (4 * px + q != idx) m2 = fmaxf(m2, e[q]);
+                for (int q = 0; q < 2; ++q)
+                    if (2 * px + q != idx) m2 = fmaxf(m2, e[q]);
                 m2 = row16_max(m2);
+                m2 = fmaxf(m2, swz_xor16(m2));
                 if (rv) {
                     const int64_t o = r0 + r - A.row_begin;
                     if (A.post)
 #pragma unroll
-                        for (int q = 0; q < 4; ++q)
-                            if (cok[q]) A.post[o * W + 4 * px + q] = e[q];
+                        for (int q = 0; q < 2; ++q)
+                            if (cok[q]) A.post[o * W + 2 * px + q] = e[q];
                     if (px == 0) {
                         if (A.argmax) A.argmax[o] = idx;
                         if (A.margin) A.margin[o] = m1 - m2;
@@ -2290,7 +2300,7 @@ __global__ __launch_bounds__(kThreads) void pass_kr_kernel(PassArgs A) {
             }
             if (++nfw == kKrFlush) {                       // W_t sums: FP32 over 16 tiles
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < 2; ++q) {
                     wacc[q] += (double)accW[q];
                     accW[q] = 0.f;
                 }
@@ -2336,9 +2346,8 @@ __global__ __launch_bounds__(kThreads) void pass_kr_kernel(PassArgs A) {
         }
     }
     fold();
-    if (wave < 4)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) wacc[q] += (double)accW[q];
+    for (int q = 0; q < 2; ++q) wacc[q] += (double)accW[q];
 
     // ---- per-workgroup partials: S (2D), W_t (Wp), sum lse', sum w C, rows
     __syncthreads();
