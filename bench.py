@@ -82,9 +82,18 @@ def time_em(em, steps: int, warmup: int, state0):
     return dt, (ms / n if n else float("nan")), n
 
 
-def leg(em, N, W, steps, warmup, state0, corr_prec=None):
+def sym_factored_flops(N, K, L, W):
+    """Matrix-core flops of the factored pass over a window symmetric about offset 0: the cosine
+    and sine products for C (2 x 2 N K M) and for U (2 x 2 N K M) over the M = L/2 + 1 (full
+    search) or (W + 1) / 2 half-window offsets."""
+    M = L // 2 + 1 if W == L else (W + 1) // 2
+    return 8.0 * N * K * M
+
+
+def leg(em, N, W, steps, warmup, state0, corr_prec=None, mfma_flops=None):
     """Time one EM configuration; with corr_prec, also the matrix-core rate of its correlation
-    GEMM (algorithmic flops: products x 2 x N x 2D x W per pass)."""
+    GEMM (algorithmic flops: products x 2 x N x 2D x W per pass); with mfma_flops, the FP32
+    matrix-core rate of that many flops per pass."""
     info = em.info()
     dt, pass_ms, n = time_em(em, steps, warmup, state0)
     rowbytes = info["bytes_per_row"]
@@ -98,6 +107,10 @@ def leg(em, N, W, steps, warmup, state0, corr_prec=None):
         tf = flops / (pass_ms * 1e-3) / 1e12
         r["mfma"] = {"algorithmic_flop_per_pass": flops, "achieved_tflops": tf,
                      "peak_tflops": PEAK_TFLOPS[corr_prec], "frac": tf / PEAK_TFLOPS[corr_prec]}
+    elif mfma_flops is not None:
+        tf = mfma_flops / (pass_ms * 1e-3) / 1e12
+        r["mfma"] = {"algorithmic_flop_per_pass": mfma_flops, "achieved_tflops": tf,
+                     "peak_tflops": PEAK_TFLOPS["fp32"], "frac": tf / PEAK_TFLOPS["fp32"]}
     return r
 
 
@@ -250,8 +263,10 @@ def main():
         for form, kw, prec in (("correlation_gemm", {}, "fp32"), ("factored", {"factored": True}, "fp32"),
                                ("correlation_gemm", {}, "fp16")):
             ef = EM(obs, K=w.K, Q=w.Q, L=w.L, sigma2=s2, precision=prec, timing=True, a0=ar, **kw)
+            sym = ef.info()["kernel"].startswith("pass_fs_kernel")
             r = leg(ef, w.N, w.L, nsteps, nwarm, (ar, uni, 0),
-                    corr_prec=prec if form == "correlation_gemm" else None)
+                    corr_prec=prec if form == "correlation_gemm" else None,
+                    mfma_flops=sym_factored_flops(w.N, w.K, w.L, w.L) if sym else None)
             ef.close()
             if prec == "fp32":
                 comp[form]["full_fp32"] = r
@@ -368,6 +383,8 @@ def main():
     cg = comp["correlation_gemm"]
     north = (cg["windowed_bf16x3"]["iter_per_s"] / cg["full_fp32"]["iter_per_s"]
              if "windowed_bf16x3" in cg and "full_fp32" in cg else None)
+    north16 = (cg["windowed_fp16"]["iter_per_s"] / cg["full_fp32"]["iter_per_s"]
+               if "windowed_fp16" in cg and "full_fp32" in cg else None)
     out = {
         "metric": METRIC,
         "value": iters_s,
@@ -399,6 +416,8 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_per_launch},
         "speedup_vs_full_fp32": north,
         "speedup_vs_full_fp32_pair": "correlation GEMM: windowed bf16x3 over full-search FP32",
+        "speedup_vs_full_fp32_fp16": north16,
+        "speedup_vs_full_fp32_fp16_pair": "correlation GEMM: windowed fp16 over full-search FP32",
         "comparisons": comp,
         "variants": variants,
         "large_image": large,

@@ -393,25 +393,26 @@ em_status run_pass(em_ctx *c, int flags, int64_t r0, int64_t r1, const double *a
     int grid = use_partials ? c->grid : (int)(ntiles < c->grid ? ntiles : c->grid);
     if (grid < 1) grid = 1;
     const bool ev = timed && c->timing && c->ev_used + 2 <= 2 * kTimingEvents;
-    if (ev) HIPCHK(c, hipEventRecord(c->ev[c->ev_used], c->stream));
+    if (ev) set_pass_events(c->ev[c->ev_used], c->ev[c->ev_used + 1]);
+    hipError_t e;
     if (c->kr)
-        HIPCHK(c, launch_pass_kr(c->prec, c->krNT, A, grid, c->lds, c->stream));
+        e = launch_pass_kr(c->prec, c->krNT, A, grid, c->lds, c->stream);
     else if (c->gm)
-        HIPCHK(c, launch_pass_gm(c->gmNT, A, grid, c->lds, c->stream));
+        e = launch_pass_gm(c->gmNT, A, grid, c->lds, c->stream);
     else if (c->ks)
-        HIPCHK(c, launch_pass_ks(c->prec, c->BM, c->ksNT, c->ksKSS, A, grid, c->lds, c->stream));
+        e = launch_pass_ks(c->prec, c->BM, c->ksNT, c->ksKSS, A, grid, c->lds, c->stream);
     else if (c->wide)
-        HIPCHK(c, launch_pass_wide(c->prec, c->wNTW, c->wUR, A, grid, c->lds, c->stream));
+        e = launch_pass_wide(c->prec, c->wNTW, c->wUR, A, grid, c->lds, c->stream);
     else if (c->fs && !(flags & (PF_QUERY | PF_STORE_LSE | PF_LOAD_LSE)))
-        HIPCHK(c, launch_pass_fs(c->prec, c->fsMTW, A, grid, c->fsLds, c->stream));
+        e = launch_pass_fs(c->prec, c->fsMTW, A, grid, c->fsLds, c->stream);
     else if (c->fac)
-        HIPCHK(c, launch_pass_fac(c->prec, c->fWIDE, c->fKCM, c->fEPL, A, grid, c->lds, c->stream));
+        e = launch_pass_fac(c->prec, c->fWIDE, c->fKCM, c->fEPL, A, grid, c->lds, c->stream);
     else
-        HIPCHK(c, launch_pass(c->prec, c->BM, c->WM, c->LD, A, grid, c->lds, c->stream));
-    if (ev) {
-        HIPCHK(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
-        c->ev_used += 2;
-    }
+        e = launch_pass(c->prec, c->BM, c->WM, c->LD, A, grid, c->lds, c->stream);
+    set_pass_events(nullptr, nullptr);
+    if (e != hipSuccess)
+        return fail(c, EM_EDEVICE, std::string("E+M pass launch failed: ") + hipGetErrorString(e));
+    if (ev) c->ev_used += 2;
     return EM_OK;
 }
 

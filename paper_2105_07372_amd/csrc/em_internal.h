@@ -115,6 +115,9 @@ hipError_t launch_scale(const double *in, double *out, int n, double factor, hip
 hipError_t launch_template(const TplArgs &a, hipStream_t s);
 hipError_t launch_pass(int prec, int BM, int WM, int LD, const PassArgs &a, int grid, size_t lds,
                        hipStream_t s);
+// Events for the next E+M pass launch of the calling thread (recorded by the dispatch, so they
+// time the kernel alone); (null, null) turns it off.  Every launch_pass* honours them.
+void set_pass_events(hipEvent_t start, hipEvent_t stop);
 // The fixed-order sum of G rows of ncols partials into red, then the finalize on red (F.red must
 // be red), in one launch.  count: one device counter per context, 0 before the first launch and
 // left at 0 by every launch; launches that share it must not overlap.

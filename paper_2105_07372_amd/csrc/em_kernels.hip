@@ -15,6 +15,7 @@
 // left out of the pass (they cancel in the posteriors) and added back in FP64 in the finalize.
 #include "em_internal.h"
 
+#include <hip/hip_ext.h>
 #include <math.h>
 #include <stdio.h>
 
@@ -4229,6 +4230,21 @@ size_t pass_lds_bytes(int prec, int BM, int K, int Dp, int Wp, int LD) {
 
 typedef void (*pass_fn)(PassArgs);
 
+// Events that time the next E+M pass launch of this host thread (the dispatch itself records
+// them, so they bracket the kernel alone); null: untimed.
+static thread_local hipEvent_t g_pass_ev[2] = {nullptr, nullptr};
+void set_pass_events(hipEvent_t start, hipEvent_t stop) {
+    g_pass_ev[0] = start;
+    g_pass_ev[1] = stop;
+}
+static void launch_pass_fn(pass_fn f, int grid, size_t lds, hipStream_t s, const PassArgs &a) {
+    if (g_pass_ev[0] || g_pass_ev[1])
+        hipExtLaunchKernelGGL(f, dim3(grid), dim3(kThreads), (uint32_t)lds, s, g_pass_ev[0],
+                              g_pass_ev[1], 0u, a);
+    else
+        hipLaunchKernelGGL(f, dim3(grid), dim3(kThreads), lds, s, a);
+}
+
 // General pass variants: (precision, rows per tile, waves along rows, loader).
 #define SEM_PASS_VARIANTS(X)                                                                   \
     X(P_F64, 8, 1, 0) X(P_F64, 16, 1, 0) X(P_F64, 32, 1, 0) X(P_F64, 16, 1, 1)                 \
@@ -4280,7 +4296,7 @@ hipError_t launch_pass(int prec, int BM, int WM, int LD, const PassArgs &a, int 
                        hipStream_t s) {
     pass_fn f = find_pass(prec, BM, WM, LD);
     if (!f) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(f, dim3(grid), dim3(kThreads), lds, s, a);
+    launch_pass_fn(f, grid, lds, s, a);
     return hipGetLastError();
 }
 
@@ -4319,7 +4335,7 @@ hipError_t launch_pass_ks(int prec, int BM, int NT, int KSS, const PassArgs &a, 
                           size_t lds, hipStream_t s) {
     pass_fn f = find_ks(prec, BM, NT, KSS, (a.flags & PF_QUERY) ? 1 : 0);
     if (!f) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(f, dim3(grid), dim3(kThreads), lds, s, a);
+    launch_pass_fn(f, grid, lds, s, a);
     return hipGetLastError();
 }
 
@@ -4373,7 +4389,7 @@ hipError_t launch_pass_kr(int prec, int NT, const PassArgs &a, int grid, size_t 
                           hipStream_t s) {
     pass_fn f = find_kr(prec, NT, (a.flags & PF_QUERY) ? 1 : 0);
     if (!f) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(f, dim3(grid), dim3(kThreads), lds, s, a);
+    launch_pass_fn(f, grid, lds, s, a);
     return hipGetLastError();
 }
 
@@ -4422,7 +4438,7 @@ bool gm_plan(int prec, int D, int K, int Q, int Wp, size_t lds_max, int *NTC, si
 hipError_t launch_pass_gm(int NTC, const PassArgs &a, int grid, size_t lds, hipStream_t s) {
     pass_fn f = find_gm(NTC, (a.flags & PF_QUERY) ? 1 : 0);
     if (!f) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(f, dim3(grid), dim3(kThreads), lds, s, a);
+    launch_pass_fn(f, grid, lds, s, a);
     return hipGetLastError();
 }
 
@@ -4474,7 +4490,7 @@ hipError_t launch_pass_wide(int prec, int NTW, int UR, const PassArgs &a, int gr
                             hipStream_t s) {
     pass_fn f = find_wide(prec, NTW, UR);
     if (!f) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(f, dim3(grid), dim3(kThreads), lds, s, a);
+    launch_pass_fn(f, grid, lds, s, a);
     return hipGetLastError();
 }
 
@@ -4539,7 +4555,7 @@ hipError_t launch_pass_fac(int prec, int WIDE, int KCM, int EPL, const PassArgs 
                            size_t lds, hipStream_t s) {
     pass_fn f = find_fac(prec, WIDE, KCM, EPL);
     if (!f) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(f, dim3(grid), dim3(kThreads), lds, s, a);
+    launch_pass_fn(f, grid, lds, s, a);
     return hipGetLastError();
 }
 
@@ -4595,7 +4611,7 @@ hipError_t launch_pass_fs(int prec, int MTW, const PassArgs &a, int grid, size_t
                           hipStream_t s) {
     pass_fn f = find_fs(prec, MTW);
     if (!f) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(f, dim3(grid), dim3(kThreads), lds, s, a);
+    launch_pass_fn(f, grid, lds, s, a);
     return hipGetLastError();
 }
 
