@@ -12,7 +12,8 @@ reported only between runs of the same formulation:
     the W rotated templates on matrix cores (bf16 hi+lo or fp16 observations against a hi+lo
     template; the full-search baseline in FP32 over all L rotations);
   * the factored E-step, an exact rewrite through the per-frequency sums
-    c_jk = sum_q conj(v_jkq) a_kq (full search and window alike).
+    c_jk = sum_q conj(v_jkq) a_kq (full search and window alike; over a window symmetric about
+    offset 0, such as the full search, with the offsets +m and -m paired).
 The headline (`value`) is the windowed run selected by --precision / --correlation.  The same run
 times the refined-resolution window, the direct full search in fp16, the large-image workload
 (N=10^6, D=2048, L=720, W=181 and 91, fp16), Synchronize and Match, the accuracy against the
@@ -58,7 +59,7 @@ def pmc_traffic(variant: str):
     if not os.path.exists(path):
         return None
     try:
-        e = json.load(open(path)).get(variant)
+        e = json.load(open(path)).get("kernels", {}).get(variant)
         if not e or e.get("kernel_source_sha") != kernel_source_hash():
             return None
         return float(e["hbm_bytes_per_launch"])
