@@ -297,6 +297,43 @@ def main():
         variants["windowed_refined_bf16x3"] = leg(e2, w.N, W, args.steps, args.warmup,
                                                   (a0, rb_ang, 0), "bf16x3")
         e2.close()
+        # plain EM in FP64 on the small workload (N = 1000, D = 128, L = 64, all rotations,
+        # uniform start, random a_0): 20 iterations, as the workload states
+        w1 = wl.WORKLOADS["c1"]
+        a1t = wl.image(w1, 0)
+        V1 = wl.observations(w1, 0, a=a1t)
+        ar1 = wl.random_init(w1, 0)
+        e1 = EM(torch.from_numpy(V1).to(dev), K=w1.K, Q=w1.Q, L=w1.L,
+                sigma2=wl.noise_variance(a1t, w1.snr), precision="fp64", timing=True, a0=ar1)
+        variants["plain_em_fp64_small"] = leg(e1, w1.N, w1.L, 20, 2,
+                                              (ar1, np.full(w1.L, 1.0 / w1.L), 0))
+        variants["plain_em_fp64_small"]["workload"] = (
+            f"plain EM N={w1.N} D={w1.D} L={w1.L} FP64, 20 iterations")
+        e1.close()
+        # the differentiable log-likelihood on the windowed workload: one forward pass (per-row
+        # log-sum-exp checkpoint) and one adjoint pass (recomputed posteriors), FP32 matrix-core
+        # correlations with FP64 reductions
+        e4 = windowed("fp32", False)
+        a_d = torch.from_numpy(a0).to(dev)
+        eta_d = torch.from_numpy(np.log(np.maximum(rb, 1e-30))).to(dev)
+        ga = torch.empty_like(a_d)
+        ge = torch.empty_like(eta_d)
+        for _ in range(2):
+            e4.loglik_fwd(a_d, s2, eta_d)
+            e4.loglik_bwd(1.0, ga, ge)
+        torch.cuda.synchronize()
+        nad = 10
+        t0 = time.perf_counter()
+        for _ in range(nad):
+            e4.loglik_fwd(a_d, s2, eta_d)
+            e4.loglik_bwd(1.0, ga, ge)
+        torch.cuda.synchronize()
+        dta = (time.perf_counter() - t0) / nad
+        variants["adjoint_fp32"] = {
+            "workload": f"loglik forward + adjoint N={w.N} D={w.D} W={W}, FP32, FP64 reductions",
+            "ms_per_forward_and_adjoint": dta * 1e3, "kernel": e4.info()["kernel"]}
+        e4.close()
+        log(f"bench: adjoint {dta * 1e3:.2f} ms per forward + adjoint")
     large = None
     if not args.no_large:
         large = large_image_legs(args, dev)
