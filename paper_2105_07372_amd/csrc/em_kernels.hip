@@ -4006,43 +4006,18 @@ __device__ void finalize_body(const FinArgs &F) {
         if (k < K && qp == 0) ck[k] = make_double2(cr, ci);
     }
     __syncthreads();
-    // stopping metric min_l ||a_new - exp(-2 pi i kbar l / L) a_t||^2 and the entropy of rho_{t+1}:
-    // Re sum_k c_k z^k at z = exp(-2 pi i l / L) by Horner's rule (|z| = 1, so the rounding error
-    // stays within about 2 K eps sum_k |c_k|), one rotation per thread
-    double best = INFINITY;
-    for (int l = t; l < L; l += kFinThreads) {
-        const double2 p = l == t ? ph0 : F.phase[l];          // exp(+2 pi i l / L)
-        const double zx = p.x, zy = -p.y;
-        double hx = ck[K - 1].x, hy = ck[K - 1].y;
-#pragma unroll 4
-        for (int k = K - 2; k >= 0; --k) {
-            const double2 c = ck[k];
-            const double nx = fma(hx, zx, fma(-hy, zy, c.x));
-            hy = fma(hx, zy, fma(hy, zx, c.y));
-            hx = nx;
-        }
-        best = fmin(best, nn2 + an2 - 2.0 * hx);
-    }
+    // rho_{t+1}, its log (-inf on zero entries and on the padding up to Wp) and a_{t+1}, stored
+    // at once (nothing below changes them)
     const double rtot = 1.0 / tot;
-    double rn[WPF], ent = 0.0;
-#pragma unroll
-    for (int c = 0; c < WPF; ++c) {
-        rn[c] = F.update_rho ? (wt[c] + F.gamma * rb[c]) * rtot : ri[c];
-        if (t + c * kFinThreads < W && rn[c] > 0.0) ent -= rn[c] * log(rn[c]);
-    }
-    {
-        double mx = -best;
-        fin_block_max_sum(mx, ent, sh);
-        best = -mx;
-    }
-    // rho_{t+1} and its log (-inf on zero entries and on the padding up to Wp), a_{t+1}
+    double ent = 0.0;
 #pragma unroll
     for (int c = 0; c < WPF; ++c) {
         const int i = t + c * kFinThreads;
         if (i >= F.Wp) continue;
-        const double r = i < W ? rn[c] : 0.0;
-        if (i < W && F.update_rho) F.rho[i] = r;
+        const double r = i < W ? (F.update_rho ? (wt[c] + F.gamma * rb[c]) * rtot : ri[c]) : 0.0;
         const double l = r > 0.0 ? log(r) : -INFINITY;
+        if (r > 0.0) ent -= r * l;
+        if (i < W && F.update_rho) F.rho[i] = r;
         F.logrho32[i] = (float)l;
         F.logrho64[i] = l;
     }
@@ -4050,6 +4025,47 @@ __device__ void finalize_body(const FinArgs &F) {
     for (int c = 0; c < DPF; ++c) {
         const int d = t + c * kFinThreads;
         if (d < D) ((double2 *)F.a)[d] = an[c];
+    }
+    // stopping metric min_l ||a_new - exp(-2 pi i kbar l / L) a_t||^2: Re sum_k c_k z^k at
+    // z = exp(-2 pi i l / L), one rotation per thread, as four interleaved Horner chains in z^4
+    // (p = h_0 + z (h_1 + z (h_2 + z h_3)), h_r = sum_j c_{4j+r} z^{4j}); |z| = 1, so the rounding
+    // error stays within a few K eps sum_k |c_k|
+    double best = INFINITY;
+    const int J = (K + 3) / 4;
+    for (int l = t; l < L; l += kFinThreads) {
+        const double2 p = l == t ? ph0 : F.phase[l];          // exp(+2 pi i l / L)
+        const double zx = p.x, zy = -p.y;
+        const double z2x = zx * zx - zy * zy, z2y = 2.0 * zx * zy;
+        const double wx = z2x * z2x - z2y * z2y, wy = 2.0 * z2x * z2y;
+        double hx[4], hy[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int k = 4 * (J - 1) + r;
+            hx[r] = k < K ? ck[k].x : 0.0;
+            hy[r] = k < K ? ck[k].y : 0.0;
+        }
+        for (int j = J - 2; j >= 0; --j) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const double2 c = ck[4 * j + r];
+                const double nx = fma(hx[r], wx, fma(-hy[r], wy, c.x));
+                hy[r] = fma(hx[r], wy, fma(hy[r], wx, c.y));
+                hx[r] = nx;
+            }
+        }
+        double px = hx[3], py = hy[3];
+#pragma unroll
+        for (int r = 2; r >= 0; --r) {
+            const double nx = fma(px, zx, fma(-py, zy, hx[r]));
+            py = fma(px, zy, fma(py, zx, hy[r]));
+            px = nx;
+        }
+        best = fmin(best, nn2 + an2 - 2.0 * px);
+    }
+    {
+        double mx = -best;
+        fin_block_max_sum(mx, ent, sh);
+        best = -mx;
     }
     if (t == 0) {
         double *rec = F.stats + (it % kStatsCap) * 6;
