@@ -44,7 +44,7 @@ struct em_ctx {
     int wNTW = 0, wUR = 0;
     bool fac = false;     // factored pass (per-frequency sums; no template)
     bool fs = false;      // ... and its symmetric-window form for the EM and log-likelihood passes
-    int fsMTW = 0;
+    int fsMTW = 0, fsE = 8;
     size_t fsLds = 0;
     bool kr = false;      // row-stream correlation pass (template in registers, rows via LDS)
     int krNT = 0;
@@ -174,12 +174,13 @@ em_status plan(em_ctx *c, size_t lds_max) {
             c->fEPL = EPL;
             c->WM = 0;
             c->lds = lds;
-            int MTW = 0;
+            int MTW = 0, E = 8;
             size_t fl = 0;
             if (fs_plan(c->prec, c->D, c->Q, c->K, c->L, c->lo, c->W, c->Wp, !c->has_angles,
-                        lds_max, &MTW, &fl)) {
+                        lds_max, &MTW, &E, &fl)) {
                 c->fs = true;
                 c->fsMTW = MTW;
+                c->fsE = E;
                 c->fsLds = fl;
             }
             return EM_OK;
@@ -404,7 +405,7 @@ em_status run_pass(em_ctx *c, int flags, int64_t r0, int64_t r1, const double *a
     else if (c->wide)
         e = launch_pass_wide(c->prec, c->wNTW, c->wUR, A, grid, c->lds, c->stream);
     else if (c->fs && !(flags & (PF_QUERY | PF_STORE_LSE | PF_LOAD_LSE)))
-        e = launch_pass_fs(c->prec, c->fsMTW, A, grid, c->fsLds, c->stream);
+        e = launch_pass_fs(c->prec, c->fsMTW, c->fsE, A, grid, c->fsLds, c->stream);
     else if (c->fac)
         e = launch_pass_fac(c->prec, c->fWIDE, c->fKCM, c->fEPL, A, grid, c->lds, c->stream);
     else
@@ -576,7 +577,8 @@ em_status em_init(em_ctx **out, const em_params *p, const void *obs_dev, const d
         }
         int occ_fs = 1;
         if (c->fs) {   // both kernels fill the same partial rows: the smaller resident grid
-            if (pass_fs_setup(c->prec, c->fsMTW, c->fsLds, &occ_fs) != hipSuccess || occ_fs < 1) {
+            if (pass_fs_setup(c->prec, c->fsMTW, c->fsE, c->fsLds, &occ_fs) != hipSuccess ||
+                occ_fs < 1) {
                 (void)hipGetLastError();
                 occ_fs = 1;
             }
@@ -1201,7 +1203,7 @@ em_status em_get_info(const em_ctx *c, em_info *info) {
     info->bytes_per_row = c->rowbytes;
     info->lds_bytes = (int64_t)(c->fs ? c->fsLds : c->lds);
     std::snprintf(info->kernel, sizeof info->kernel, "%s",
-                  c->fs     ? pass_fs_name(c->prec, c->fsMTW)
+                  c->fs     ? pass_fs_name(c->prec, c->fsMTW, c->fsE)
                   : c->kr   ? pass_kr_name(c->prec, c->krNT)
                   : c->gm   ? pass_gm_name(c->gmNT)
                   : c->ks   ? pass_ks_name(c->prec, c->BM, c->ksNT, c->ksKSS)

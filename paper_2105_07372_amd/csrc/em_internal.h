@@ -190,13 +190,14 @@ hipError_t launch_pass_fac(int prec, int WIDE, int KCM, int EPL, const PassArgs 
 hipError_t pass_fac_setup(int prec, int WIDE, int KCM, int EPL, size_t lds, int *blocks_per_cu);
 const char *pass_fac_name(int prec, int WIDE, int KCM, int EPL);
 // The factored pass over a window symmetric about offset 0 (W = L, or lo = -h with W = 2h + 1),
-// for D = 512, K <= 32, Wp > 64 on the grid; EM and log-likelihood passes only (no posterior
+// on the grid with Wp > 64: D = 512 (K <= 32; E = 8 entries per lane) or D = 2048 in one 16-bit
+// plane (K <= 64; E = 16, rows over wave pairs); EM and log-likelihood passes only (no posterior
 // queries, no stored or loaded per-row log-sum-exps).  MTW: window tiles of 16 per wave.
 bool fs_plan(int prec, int D, int Q, int K, int L, int lo, int W, int Wp, bool grid,
-             size_t lds_max, int *MTW, size_t *lds);
-hipError_t launch_pass_fs(int prec, int MTW, const PassArgs &a, int grid, size_t lds,
+             size_t lds_max, int *MTW, int *E, size_t *lds);
+hipError_t launch_pass_fs(int prec, int MTW, int E, const PassArgs &a, int grid, size_t lds,
                           hipStream_t s);
-hipError_t pass_fs_setup(int prec, int MTW, size_t lds, int *blocks_per_cu);
-const char *pass_fs_name(int prec, int MTW);
+hipError_t pass_fs_setup(int prec, int MTW, int E, size_t lds, int *blocks_per_cu);
+const char *pass_fs_name(int prec, int MTW, int E);
 
 }  // namespace sem

@@ -3411,27 +3411,38 @@ __global__ __launch_bounds__(kThreads) void pass_fac_kernel(PassArgs A) {
 // are added in wave order by the M-step.  No posterior queries or stored log-sum-exps: those
 // passes take the plain factored kernel.
 
-constexpr int kFsKS = 8;          // k-steps of 4 over K <= 32
-constexpr int kFsTS = 36;         // stride (floats) of an offset's row of the cosine / sine table:
-                                  // both products' fragment reads fall in distinct banks
-constexpr int kFsCW = 36;         // stride (floats) of a staged c row: [q][ks] order, padded
 constexpr int kFsWFlush = 16;     // tiles of FP32 W_t partials per FP64 flush
-constexpr int kFsUS = 17;         // stride (float2) of a k row of the U^T partials: the M-step's
-                                  // reads (32 k per row j) fall in distinct banks
+
+// Geometry of the two forms: E = 8 entries per lane (D = 512, whole rows per wave, 16-row tiles,
+// K <= 32) or 16 (D = 2048 in one 16-bit plane, each row over a pair of waves, 8-row tiles,
+// K <= 64).  KS: k-steps of 4; TS / CW: row strides (floats) of the cosine / sine tables and of
+// the staged c rows, padded so that both products' fragment reads fall in distinct banks; US:
+// stride (float2) of a k row of the U^T partials (the M-step's reads, one k per lane pair, then
+// fall in distinct banks).
+template <int E>
+struct FsGeo {
+    static constexpr bool HR = E == 16;
+    static constexpr int BM = HR ? 8 : 16, RPW = 2, KS = HR ? 16 : 8, KT = KS / 4;
+    static constexpr int TS = 4 * KS + 4, CW = 4 * KS + 4, KR = 4 * KS, US = BM + 1;
+    static constexpr int NVL = HR ? 128 : 64;
+};
 
 struct FsLds {
     int off_ct, off_st, off_lr, off_c, off_x, off_u, off_sw, off_w, off_a, total;
 };
+template <int E>
 __host__ __device__ inline FsLds fs_lds(int MT, int D, int Wp) {
+    typedef FsGeo<E> G;
     FsLds l;
-    l.off_ct = 0;                                          // cos table, MT x 16 x kFsTS
-    l.off_st = l.off_ct + MT * 16 * kFsTS * 4;             // sin table
-    l.off_lr = l.off_st + MT * 16 * kFsTS * 4;             // log rho at +m, then at -m
+    l.off_ct = 0;                                          // cos table, MT x 16 x TS
+    l.off_st = l.off_ct + MT * 16 * G::TS * 4;             // sin table
+    l.off_lr = l.off_st + MT * 16 * G::TS * 4;             // log rho at +m, then at -m
     l.off_c = l.off_lr + 2 * MT * 16 * 4;                  // Re c rows, then Im c rows
-    l.off_x = l.off_c + 2 * 16 * kFsCW * 4;                // (max, sum) per wave and row
+    l.off_x = l.off_c + 2 * 16 * G::CW * 4;                // (max, sum) per wave and row
     l.off_u = l.off_x + 8 * 16 * 8;                        // U^T partials: [wave][k][row] float2
-    l.off_sw = l.off_u + 8 * 32 * kFsUS * 8;               // M-step partials per wave
-    l.off_w = align_up(l.off_sw + 8 * (9 * D / 8) * 8, 16);  // W_t (FP64)
+    l.off_sw = l.off_u + 8 * G::KR * G::US * 8;            // M-step partials
+    // (E = 8: per wave, FP32, [w][9 (d / 8) + d % 8]; E = 16: one FP64 copy of S)
+    l.off_w = align_up(l.off_sw + (G::HR ? D * 16 : 8 * (9 * D / 8) * 8), 16);  // W_t (FP64)
     l.off_a = align_up(l.off_w + Wp * 8, 16);              // a (FP32), lane-major
     l.total = l.off_a + D * 8;
     return l;
@@ -3453,9 +3464,14 @@ __host__ __device__ inline int fs_mirror(int m, int L, int lo, int W) {
     return (i < W && i != fs_plus(m, L, lo)) ? i : -1;
 }
 
-template <int P, int MTW>
+template <int P, int MTW, int E>
 __global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
-    constexpr int EPL = 8, RPW = 2, BM = 16;
+    typedef FsGeo<E> G;
+    constexpr bool HR = G::HR;
+    constexpr int EPL = E, RPW = G::RPW, BM = G::BM, KS = G::KS, KT = G::KT;
+    constexpr int TS = G::TS, CW = G::CW, KR = G::KR, US = G::US, NVL = G::NVL;
+    constexpr int DPT = NVL * EPL / kThreads;          // S entries per thread (1 or 4)
+    static_assert(!HR || P == P_F16 || P == P_BF16, "rows over wave pairs: one 16-bit plane");
     if ((A.flags & PF_CHECK_STOP) && *A.stopped) return;
 
     extern __shared__ __align__(16) uint8_t smem[];
@@ -3464,7 +3480,9 @@ __global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
     const int g = lane >> 4, c16 = lane & 15;
     const int K = A.K, D = A.D, L = A.L, lo = A.lo, W = A.W, Wp = A.Wp;
     const int M = fs_halves(L, lo, W), MT = (M + 15) / 16;
-    const FsLds LY = fs_lds(MT, D, Wp);
+    const FsLds LY = fs_lds<E>(MT, D, Wp);
+    const int hh = HR ? (wave & 1) : 0, rg = HR ? (wave >> 1) : wave;   // half, row group
+    const int vl = 64 * hh + lane;                 // this lane's place in the row
     float *ct = (float *)(smem + LY.off_ct);
     float *st = (float *)(smem + LY.off_st);
     float *lrp = (float *)(smem + LY.off_lr);
@@ -3476,10 +3494,10 @@ __global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
     double *wt64 = (double *)(smem + LY.off_w);
     float2 *as = (float2 *)(smem + LY.off_a);
 
-    // tables: ct / st entry [m][k] (row stride kFsTS) = cos / sin (kbar_k theta_m) (zero past M
+    // tables: ct / st entry [m][k] (row stride TS) = cos / sin (kbar_k theta_m) (zero past M
     // and K; sines zero where the offset is its own mirror)
-    for (int x = tid; x < MT * 16 * kFsTS; x += kThreads) {
-        const int m = x / kFsTS, k = x % kFsTS;
+    for (int x = tid; x < MT * 16 * TS; x += kThreads) {
+        const int m = x / TS, k = x % TS;
         float cv = 0.f, sv = 0.f;
         if (m < M && k < K) {
             const float *e = A.E2 + (int64_t)fs_plus(m, L, lo) * 2 * K;
@@ -3499,16 +3517,19 @@ __global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
         lrp[m] = p;
         lrm[m] = q;
     }
-    for (int x = tid; x < 2 * 16 * kFsCW; x += kThreads) cs[x] = 0.f;   // k >= K stays zero
+    // c rows past the tile's rows and columns k >= K stay zero
+    for (int x = tid; x < 2 * 16 * CW; x += kThreads) cs[x] = 0.f;
     // the exchange slots of waves without window tiles keep (-inf, 0) and zero U partials
     for (int x = tid; x < 8 * 16; x += kThreads) xs[x] = make_float2(-INFINITY, 0.f);
-    for (int x = tid; x < 8 * 32 * kFsUS; x += kThreads) up[x] = make_float2(0.f, 0.f);
+    for (int x = tid; x < 8 * KR * US; x += kThreads) up[x] = make_float2(0.f, 0.f);
     for (int i = tid; i < Wp; i += kThreads) wt64[i] = 0.0;
     for (int d = tid; d < D; d += kThreads)
-        as[(d % EPL) * 64 + d / EPL] = make_float2((float)A.a[2 * d], (float)A.a[2 * d + 1]);
+        as[(d % EPL) * NVL + d / EPL] = make_float2((float)A.a[2 * d], (float)A.a[2 * d + 1]);
+    if constexpr (HR)
+        for (int d = tid; d < D; d += kThreads) ((double2 *)Sw)[d] = make_double2(0.0, 0.0);
     __syncthreads();
 
-    const int kl = EPL * lane / A.Q;               // this lane's angular frequency index
+    const int kl = EPL * vl / A.Q;                 // this lane's angular frequency index
     const int LPK = A.Q / EPL;
     float lpk_f[4];
 #pragma unroll
@@ -3516,17 +3537,18 @@ __global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
     const float coef = (float)A.coef;
     const int nwu = MT < 8 ? MT : 8;                // waves holding window tiles
 
-    PassAcc<1> acc;
+    PassAcc<DPT> acc;
     acc.init();
     const int64_t ntiles = (A.row_end - A.row_begin + BM - 1) / BM;
     FacRow<P, EPL> vn[RPW];
     float rsn[RPW];
     auto load_tile = [&](int64_t t) {
-        const int64_t rb = A.row_begin + t * BM + RPW * wave;
+        const int64_t rb = A.row_begin + t * BM + RPW * rg;
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
             const int64_t row = rb + r < A.row_end ? rb + r : A.row_end - 1;
-            vn[r].load(A.V + row * A.rowbytes, A.Dp, lane);
+            // (the second half of a split row starts after D/2 entries of 4 bytes)
+            vn[r].load(A.V + row * A.rowbytes + (HR ? hh * (D / 2) * 4 : 0), A.Dp, lane);
             rsn[r] = A.rowscale ? A.rowscale[row] : 1.0f;
         }
     };
@@ -3535,6 +3557,23 @@ __global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
     for (int e = 0; e < EPL; ++e) sr[e] = si[e] = 0.f;
     int nacc = 0;
     auto flush_s = [&]() {
+      if constexpr (HR) {
+        // the four row groups add their FP32 partials into the FP64 copy of S in order (the two
+        // halves of a group own disjoint entries)
+        double2 *Sd = (double2 *)Sw;
+        const int d0 = EPL * vl;
+        for (int w = 0; w < 4; ++w) {
+            if (rg == w)
+#pragma unroll
+                for (int e = 0; e < EPL; ++e) {
+                    double2 t = Sd[d0 + e];
+                    t.x += (double)sr[e];
+                    t.y += (double)si[e];
+                    Sd[d0 + e] = t;
+                }
+            lds_barrier();
+        }
+      } else {
         // wave w's partials at [w][9 (d / 8) + d % 8], then summed in wave order per entry
         constexpr int SWS = 9 * 512 / 8;                   // (D = 512)
 #pragma unroll
@@ -3553,6 +3592,7 @@ __global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
             acc.S[0].x += (double)s.x;
             acc.S[0].y += (double)s.y;
         }
+      }
 #pragma unroll
         for (int e = 0; e < EPL; ++e) sr[e] = si[e] = 0.f;
         nacc = 0;
@@ -3605,10 +3645,10 @@ __global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
         // lane's coefficients read from LDS once per tile)
         float2 areg[EPL];
 #pragma unroll
-        for (int e = 0; e < EPL; ++e) areg[e] = as[e * 64 + lane];
+        for (int e = 0; e < EPL; ++e) areg[e] = as[e * NVL + vl];
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
-            const int j = RPW * wave + r;
+            const int j = RPW * rg + r;
             float cr = 0.f, ci = 0.f;
 #pragma unroll
             for (int e = 0; e < EPL; ++e) {
@@ -3626,25 +3666,18 @@ __global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
             }
             const float u = j < rows ? rsc[r] : 1.0f;
             if ((lane & (LPK - 1)) == 0) {
-                const int o = j * kFsCW + (kl & 3) * 8 + (kl >> 2);
+                const int o = j * CW + (kl & 3) * KS + (kl >> 2);
                 cs[o] = cr * (coef * u);
-                cs[16 * kFsCW + o] = ci * (coef * u);
+                cs[16 * CW + o] = ci * (coef * u);
             }
         }
         lds_barrier();
         if (pf && wave >= 4) load_tile(tile + gridDim.x);
 
         // ---- P^T and Q^T for this wave's window tiles; log-weights at +m and -m
-        float br[kFsKS], bi[kFsKS];
-        {
-            const float4 *pr = (const float4 *)(cs + c16 * kFsCW + 8 * g);
-            const float4 *pi = (const float4 *)(cs + 16 * kFsCW + c16 * kFsCW + 8 * g);
-            const float4 r0v = pr[0], r1v = pr[1], i0v = pi[0], i1v = pi[1];
-            br[0] = r0v.x; br[1] = r0v.y; br[2] = r0v.z; br[3] = r0v.w;
-            br[4] = r1v.x; br[5] = r1v.y; br[6] = r1v.z; br[7] = r1v.w;
-            bi[0] = i0v.x; bi[1] = i0v.y; bi[2] = i0v.z; bi[3] = i0v.w;
-            bi[4] = i1v.x; bi[5] = i1v.y; bi[6] = i1v.z; bi[7] = i1v.w;
-        }
+        // B fragments of k-step ks: c[j = lane % 16][4 ks + lane / 16], KS consecutive floats
+        const float4 *pbr = (const float4 *)(cs + c16 * CW + KS * g);
+        const float4 *pbi = (const float4 *)(cs + 16 * CW + c16 * CW + KS * g);
         float lp[MTW][4], lm[MTW][4];
         float mloc = -INFINITY;
 #pragma unroll
@@ -3657,12 +3690,19 @@ __global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
             }
             f32x4 pa = (f32x4){0.f, 0.f, 0.f, 0.f}, qa = pa;
             // A fragment of k-step ks: offset m = 16 mt + lane % 16, k = 4 ks + lane / 16
-            const float *ca = ct + (16 * mt + c16) * kFsTS + g;
-            const float *sa = st + (16 * mt + c16) * kFsTS + g;
+            const float *ca = ct + (16 * mt + c16) * TS + g;
+            const float *sa = st + (16 * mt + c16) * TS + g;
 #pragma unroll
-            for (int ks = 0; ks < kFsKS; ++ks) {
-                pa = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[4 * ks], br[ks], pa, 0, 0, 0);
-                qa = __builtin_amdgcn_mfma_f32_16x16x4f32(sa[4 * ks], bi[ks], qa, 0, 0, 0);
+            for (int k4 = 0; k4 < KS / 4; ++k4) {
+                const float4 b4r = pbr[k4], b4i = pbi[k4];
+                const float brv[4] = {b4r.x, b4r.y, b4r.z, b4r.w};
+                const float biv[4] = {b4i.x, b4i.y, b4i.z, b4i.w};
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int ks = 4 * k4 + u;
+                    pa = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[4 * ks], brv[u], pa, 0, 0, 0);
+                    qa = __builtin_amdgcn_mfma_f32_16x16x4f32(sa[4 * ks], biv[u], qa, 0, 0, 0);
+                }
             }
             const float4 lp4 = *(const float4 *)(lrp + 16 * mt + 4 * g);
             const float4 lm4 = *(const float4 *)(lrm + 16 * mt + 4 * g);
@@ -3676,15 +3716,33 @@ __global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
             }
         }
         // this wave's maximum and sum for row j over the four lane groups; its exponentials,
-        // relative to that maximum, are the B operand of the U^T product at once (the row's
-        // factor exp(m_wave - m_row) / sum, a column scale of U^T, is applied after the exchange)
+        // relative to that maximum, are the B operand of the U^T product (the row's factor
+        // exp(m_wave - m_row) / sum, a column scale of U^T, is applied after the exchange).  With
+        // 8 entries per lane the products run before the exchange, beside the exponentials; with
+        // 16 (the rows and M-step sums take twice the registers) after it.
         mloc = fmaxf(mloc, swz_xor16(mloc));
         mloc = fmaxf(mloc, __shfl_xor(mloc, 32));
         const bool accm = (A.flags & PF_ACC_M) != 0;
         float ep[MTW][4], em[MTW][4], sloc = 0.f, wcl = 0.f;
-        f32x4 ur[2], ui[2];
+        f32x4 ur[KT], ui[KT];
 #pragma unroll
-        for (int kt = 0; kt < 2; ++kt) ur[kt] = ui[kt] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        for (int kt = 0; kt < KT; ++kt) ur[kt] = ui[kt] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        // U^T = E e^T over window tile t (Re: cos with e(+m) + e(-m); Im: sin with e(+m) - e(-m));
+        // A fragment: k = 16 kt + lane % 16, offset m = 16 mt + 4 g + q
+        auto u_tile = [&](int t) {
+            const int mt = wave + 8 * t;
+            if (!accm || mt >= MT) return;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float ws = ep[t][q] + em[t][q], wd = ep[t][q] - em[t][q];
+#pragma unroll
+                for (int kt = 0; kt < KT; ++kt) {
+                    const int o = (16 * mt + 4 * g + q) * TS + 16 * kt + c16;
+                    ur[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ct[o], ws, ur[kt], 0, 0, 0);
+                    ui[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(st[o], wd, ui[kt], 0, 0, 0);
+                }
+            }
+        };
 #pragma unroll
         for (int t = 0; t < MTW; ++t) {
             const int mtl = (wave + 8 * t) < MT ? wave + 8 * t : 0;
@@ -3702,20 +3760,7 @@ __global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
                 if (fp) wcl = fmaf(ep[t][q], lp[t][q] - lpv[q], wcl);
                 if (fm) wcl = fmaf(em[t][q], lm[t][q] - lmv[q], wcl);
             }
-            // U^T = E e^T over this window tile (Re: cos with e(+m) + e(-m); Im: sin with
-            // e(+m) - e(-m)); A fragment: k = 16 kt + lane % 16, offset m = 16 mt + 4 g + q
-            const int mt = wave + 8 * t;
-            if (!accm || mt >= MT) continue;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const float ws = ep[t][q] + em[t][q], wd = ep[t][q] - em[t][q];
-#pragma unroll
-                for (int kt = 0; kt < 2; ++kt) {
-                    const int o = (16 * mt + 4 * g + q) * kFsTS + 16 * kt + c16;
-                    ur[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ct[o], ws, ur[kt], 0, 0, 0);
-                    ui[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(st[o], wd, ui[kt], 0, 0, 0);
-                }
-            }
+            if constexpr (!HR) u_tile(t);
         }
         sloc += swz_xor16(sloc);
         sloc += __shfl_xor(sloc, 32);
@@ -3750,12 +3795,16 @@ __global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
         }
         if (++nw == kFsWFlush) flush_w();
         if (!accm) continue;
-        if (wave < nwu) {
+        if constexpr (HR) {
 #pragma unroll
-            for (int kt = 0; kt < 2; ++kt)
+            for (int t = 0; t < MTW; ++t) u_tile(t);
+        }
+        if (wave < nwu && c16 < BM) {
+#pragma unroll
+            for (int kt = 0; kt < KT; ++kt)
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    up[(wave * 32 + 16 * kt + 4 * g + q) * kFsUS + c16] =
+                    up[(wave * KR + 16 * kt + 4 * g + q) * US + c16] =
                         make_float2(ur[kt][q] * scale, ui[kt][q] * scale);
         }
         lds_barrier();
@@ -3764,12 +3813,12 @@ __global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
         // the row scale; this lane's entries over this wave's rows, FP32 over kFacFlush tiles
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
-            const int j = RPW * wave + r;
+            const int j = RPW * rg + r;
             float2 u = make_float2(0.f, 0.f);
             if (j < rows) {
                 float2 ut[8];
 #pragma unroll
-                for (int w = 0; w < 8; ++w) ut[w] = up[(w * 32 + kl) * kFsUS + j];
+                for (int w = 0; w < 8; ++w) ut[w] = up[(w * KR + kl) * US + j];
 #pragma unroll
                 for (int w = 0; w < 8; ++w) {
                     u.x += ut[w].x;
@@ -3787,10 +3836,14 @@ __global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
                 si[e] = fmaf(u.y, v.x, si[e]);
             }
         }
-        if (++nacc == kFacFlush || tile + gridDim.x >= ntiles) flush_s();
+        if (++nacc == (HR ? kFacFlush16 : kFacFlush) || tile + gridDim.x >= ntiles) flush_s();
     }
     if (nw) flush_w();
     __syncthreads();
+    if constexpr (HR) {
+#pragma unroll
+        for (int cc = 0; cc < DPT; ++cc) acc.S[cc] = ((const double2 *)Sw)[tid + cc * kThreads];
+    }
     acc.wc = wc_acc;
     for (int c = 0; c < 2; ++c) {
         const int i = tid + c * kThreads;
@@ -4593,46 +4646,51 @@ const char *pass_fac_name(int prec, int WIDE, int KCM, int EPL) {
 }
 
 
-// Symmetric-window factored pass variants: (precision, window tiles per wave).
+// Symmetric-window factored pass variants: (precision, window tiles per wave, entries per lane).
 #define SEM_FS_VARIANTS(X)                                                                     \
-    X(P_F32, 1) X(P_F32, 2) X(P_BF16X3, 1) X(P_BF16X3, 2) X(P_F16, 1) X(P_F16, 2)              \
-    X(P_BF16, 1) X(P_BF16, 2)
+    X(P_F32, 1, 8) X(P_F32, 2, 8) X(P_BF16X3, 1, 8) X(P_BF16X3, 2, 8) X(P_F16, 1, 8)           \
+    X(P_F16, 2, 8) X(P_BF16, 1, 8) X(P_BF16, 2, 8) X(P_F16, 1, 16) X(P_BF16, 1, 16)
 
-static pass_fn find_fs(int prec, int MTW) {
-#define SEM_X(P, T)                                                                            \
-    if (prec == P && MTW == T) return pass_fs_kernel<P, T>;
+static pass_fn find_fs(int prec, int MTW, int E) {
+#define SEM_X(P, T, EE)                                                                        \
+    if (prec == P && MTW == T && E == EE) return pass_fs_kernel<P, T, EE>;
     SEM_FS_VARIANTS(SEM_X)
 #undef SEM_X
     return nullptr;
 }
 
 bool fs_plan(int prec, int D, int Q, int K, int L, int lo, int W, int Wp, bool grid,
-             size_t lds_max, int *MTW, size_t *lds) {
-    if (!grid || D != 512 || Q % 8 != 0 || K > 32 || Wp <= 64) return false;
-    const int lpk = Q / 8;
+             size_t lds_max, int *MTW, int *E, size_t *lds) {
+    if (!grid || Wp <= 64) return false;
+    int e = 0;
+    if (D == 512 && Q % 8 == 0 && K <= 32) e = 8;
+    else if (D == 2048 && (prec == P_F16 || prec == P_BF16) && Q % 16 == 0 && K <= 64) e = 16;
+    else return false;
+    const int lpk = Q / e;
     if (lpk & (lpk - 1)) return false;                       // lanes per frequency: 2^n
     if (W != L && !(W % 2 == 1 && fs_mod(lo + (W - 1) / 2, L) == 0))
         return false;                                        // not symmetric about offset 0
     const int MT = (fs_halves(L, lo, W) + 15) / 16;
     const int mtw = (MT + 7) / 8;
-    if (mtw > 2 || !find_fs(prec, mtw)) return false;
-    const size_t b = (size_t)fs_lds(MT, D, Wp).total;
+    if (!find_fs(prec, mtw, e)) return false;
+    const size_t b = (size_t)(e == 8 ? fs_lds<8>(MT, D, Wp) : fs_lds<16>(MT, D, Wp)).total;
     if (b > lds_max) return false;
     *MTW = mtw;
+    *E = e;
     *lds = b;
     return true;
 }
 
-hipError_t launch_pass_fs(int prec, int MTW, const PassArgs &a, int grid, size_t lds,
+hipError_t launch_pass_fs(int prec, int MTW, int E, const PassArgs &a, int grid, size_t lds,
                           hipStream_t s) {
-    pass_fn f = find_fs(prec, MTW);
+    pass_fn f = find_fs(prec, MTW, E);
     if (!f) return hipErrorInvalidValue;
     launch_pass_fn(f, grid, lds, s, a);
     return hipGetLastError();
 }
 
-hipError_t pass_fs_setup(int prec, int MTW, size_t lds, int *blocks_per_cu) {
-    pass_fn f = find_fs(prec, MTW);
+hipError_t pass_fs_setup(int prec, int MTW, int E, size_t lds, int *blocks_per_cu) {
+    pass_fn f = find_fs(prec, MTW, E);
     if (!f) return hipErrorInvalidValue;
     hipError_t e = hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
@@ -4641,9 +4699,10 @@ hipError_t pass_fs_setup(int prec, int MTW, size_t lds, int *blocks_per_cu) {
                                                         lds);
 }
 
-const char *pass_fs_name(int prec, int MTW) {
+const char *pass_fs_name(int prec, int MTW, int E) {
     static thread_local char buf[64];   // (per thread: callers copy it out)
-    snprintf(buf, sizeof buf, "pass_fs_kernel<%s,BM=16,MTW=%d>", kPrecName[prec], MTW);
+    snprintf(buf, sizeof buf, "pass_fs_kernel<%s,BM=%d,MTW=%d%s>", kPrecName[prec],
+             E == 16 ? 8 : 16, MTW, E == 16 ? ",E16" : "");
     return buf;
 }
 

@@ -225,7 +225,9 @@ def test_factored_2048_teacher_forced_step(gpu, prec, shape):
     print(f"factored D=2048 shape={shape} prec={prec} N={N} W={W}", flush=True)
     em = EM(torch.from_numpy(V.astype(np.complex64)).to(gpu), K=K, Q=Q, L=L, sigma2=s2,
             window=(lo, W), prior=rb, gamma=50.0, precision=prec, factored=True)
-    assert em.info()["kernel"].startswith("pass_fac_kernel") and "E16" in em.info()["kernel"]
+    # windows past 64 offsets (symmetric about 0) take the paired-offset kernel for EM steps
+    want = "pass_fs_kernel" if W > 64 else "pass_fac_kernel"
+    assert em.info()["kernel"].startswith(want) and "E16" in em.info()["kernel"], em.info()
     em.set_state(a_t, rho_t, 0)
     offs = oracle.offsets(lo, W)
     wg, am, mg = em.posterior()
