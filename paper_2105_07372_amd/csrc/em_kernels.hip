@@ -3796,10 +3796,37 @@ __global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
         if (++nw == kFsWFlush) flush_w();
         if (!accm) continue;
         if constexpr (HR) {
+            // two column tiles of U^T at a time (half the accumulators live), each written out
+            // before the next pair
+            static_assert(MTW == 1, "one window tile per wave");
+            const int mt = wave;
 #pragma unroll
-            for (int t = 0; t < MTW; ++t) u_tile(t);
-        }
-        if (wave < nwu && c16 < BM) {
+            for (int kp = 0; kp < KT; kp += 2) {
+                f32x4 u2r[2], u2i[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) u2r[h] = u2i[h] = (f32x4){0.f, 0.f, 0.f, 0.f};
+                if (mt < MT) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const float ws = ep[0][q] + em[0][q], wd = ep[0][q] - em[0][q];
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            const int o = (16 * mt + 4 * g + q) * TS + 16 * (kp + h) + c16;
+                            u2r[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(ct[o], ws, u2r[h], 0, 0, 0);
+                            u2i[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(st[o], wd, u2i[h], 0, 0, 0);
+                        }
+                    }
+                }
+                if (wave < nwu && c16 < BM) {
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            up[(wave * KR + 16 * (kp + h) + 4 * g + q) * US + c16] =
+                                make_float2(u2r[h][q] * scale, u2i[h][q] * scale);
+                }
+            }
+        } else if (wave < nwu) {
 #pragma unroll
             for (int kt = 0; kt < KT; ++kt)
 #pragma unroll
