@@ -2473,8 +2473,26 @@ __global__ __launch_bounds__(kThreads) void pass_gm_kernel(PassArgs A) {
     double Wacc = 0.0, acc_lse = 0.0, acc_wc = 0.0, acc_rows = 0.0;
     __syncthreads();
 
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int64_t r0 = A.row_begin + tile * kGmBM;
+    // Full rounds of 128-row tiles over the grid, then the remaining rows split evenly over the
+    // workgroups as one short tile each (a whole round of 128-row tiles for the remainder would
+    // leave most workgroups idle while a few finish it); the waves of a short tile that hold no
+    // rows skip their products.
+    const int64_t nall = A.row_end - A.row_begin;
+    const int64_t nfull = nall / ((int64_t)kGmBM * gridDim.x);
+    const int64_t rem = nall - nfull * kGmBM * gridDim.x;
+    (void)ntiles;
+    for (int64_t tile = 0; tile < nfull + (rem > 0 ? 1 : 0); ++tile) {
+        int64_t r0, rend;
+        if (tile < nfull) {
+            r0 = A.row_begin + (tile * gridDim.x + blockIdx.x) * kGmBM;
+            rend = r0 + kGmBM;
+        } else {
+            const int64_t base = A.row_begin + nfull * kGmBM * gridDim.x;
+            r0 = base + rem * blockIdx.x / gridDim.x;
+            rend = base + rem * (blockIdx.x + 1) / gridDim.x;
+        }
+        if (rend <= r0) continue;                         // (no rows here: the whole workgroup)
+        const bool wrows = r0 + 16 * wave < rend;         // this wave holds rows of the tile
         auto issue = [&](int c) {
             uint8_t *st = smem + (c & 1) * LY.stage;
             // rows: LDS slot p (16 B) of the chunk holds row p / 8, real slot (p % 8) ^ ((row >>
@@ -2483,7 +2501,7 @@ __global__ __launch_bounds__(kThreads) void pass_gm_kernel(PassArgs A) {
             for (int x = 0; x < 2; ++x) {
                 const int p = 64 * (wave + 8 * x) + lane, r = p >> 3;
                 const int sl = (p & 7) ^ ((r >> 1) & 7);
-                const int64_t row = r0 + r < A.row_end ? r0 + r : A.row_end - 1;
+                const int64_t row = r0 + r < rend ? r0 + r : rend - 1;
                 dma_to_lds<16>(A.V + row * A.rowbytes + (c * kGmKC + 4 * sl) * 4,
                                st + 64 * (wave + 8 * x) * 16);
             }
@@ -2504,6 +2522,7 @@ __global__ __launch_bounds__(kThreads) void pass_gm_kernel(PassArgs A) {
             wait_vm<0>();                                 // chunk c has landed (this wave's part)
             lds_barrier();                                // ... all of it; chunk c - 1 is consumed
             if (c + 1 < NCH) issue(c + 1);                // into the buffer chunk c - 1 used
+            if (!wrows) continue;
             const uint8_t *st = smem + (c & 1) * LY.stage;
 #pragma unroll
             for (int kk = 0; kk < 2; ++kk) {
@@ -2533,7 +2552,7 @@ __global__ __launch_bounds__(kThreads) void pass_gm_kernel(PassArgs A) {
             }
         }
         const int64_t row = r0 + rr;
-        const bool rv = row < A.row_end;
+        const bool rv = row < rend;
 
         // ---- a4: log-weights, log-sum-exp over the row's 4 lanes, posteriors (in acc)
         float mx = -INFINITY;
@@ -2660,15 +2679,15 @@ __global__ __launch_bounds__(kThreads) void pass_gm_kernel(PassArgs A) {
         // waves' sums added in wave order into the FP64 sums (E' staging area reused)
         float *swv = (float *)(smem + LY.off_sw);         // 8 waves x 2D floats
         lds_barrier();                                    // every wave is done reading E'
-        if (8 * lane < D) {
+        if (8 * lane < D) {                               // (waves without rows write zeros)
             const int k = (8 * lane) / A.Q;
             float sr[8], si[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) sr[e] = si[e] = 0.f;
 #pragma unroll 4
-            for (int jr = 0; jr < 16; ++jr) {
+            for (int jr = 0; jr < (wrows ? 16 : 0); ++jr) {
                 const int64_t rw = r0 + 16 * wave + jr;
-                const int64_t rc = rw < A.row_end ? rw : A.row_end - 1;
+                const int64_t rc = rw < rend ? rw : rend - 1;
                 const float4 *src = (const float4 *)(A.V + rc * A.rowbytes) + 4 * lane;
                 float4 v[4];
 #pragma unroll
