@@ -1184,6 +1184,53 @@ __global__ __launch_bounds__(kThreads) void pass_kernel(PassArgs A) {
 // eight partial correlations are summed in a fixed order through LDS (waves 4-7 into 0-3, then
 // ((s0 + s1) + s2) + s3), so the result does not depend on scheduling.
 
+// The inputs a template-in-registers pass builds its template from, staged in LDS once per
+// workgroup (every workgroup reads the same few KiB; read straight from global memory inside the
+// template loops, those reads queue on the same cache lines and take tens of microseconds): a_t
+// as FP32 (Re, Im) pairs (D <= 4 kThreads entries) at st, then the window's phase rows E2 (Wp
+// rows of [cos | sin] x K floats, Wp 2K <= 16 kThreads).  Returns max |Re a_d|, |Im a_d| to every
+// thread (sh8: 8 doubles of LDS); its barrier publishes the staged tables.
+constexpr int kStageA = 4, kStageE = 16;
+__device__ double stage_a_e2(const PassArgs &A, uint8_t *st, double *sh8) {
+    float2 *as = (float2 *)st;
+    float *es = (float *)(st + 8 * A.D);
+    const int t = threadIdx.x, ne = A.Wp * 2 * A.K;
+    double ar[kStageA], ai[kStageA];
+    float ev[kStageE];
+#pragma unroll
+    for (int c = 0; c < kStageA; ++c) {
+        const int d = t + c * kThreads;
+        ar[c] = d < A.D ? A.a[2 * d] : 0.0;
+        ai[c] = d < A.D ? A.a[2 * d + 1] : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < kStageE; ++c) {
+        const int x = t + c * kThreads;
+        ev[c] = x < ne ? A.E2[x] : 0.f;
+    }
+    double amax = 0.0;
+#pragma unroll
+    for (int c = 0; c < kStageA; ++c) {
+        const int d = t + c * kThreads;
+        amax = fmax(amax, fmax(fabs(ar[c]), fabs(ai[c])));
+        if (d < A.D) as[d] = make_float2((float)ar[c], (float)ai[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < kStageE; ++c) {
+        const int x = t + c * kThreads;
+        if (x < ne) es[x] = ev[c];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o));
+    if ((t & 63) == 0) sh8[t >> 6] = amax;
+    __syncthreads();
+    double r = sh8[0];
+#pragma unroll
+    for (int w = 1; w < kThreads / 64; ++w) r = fmax(r, sh8[w]);
+    return r;
+}
+__host__ __device__ inline int stage_a_e2_bytes(int D, int Wp, int K) { return 8 * D + 8 * Wp * K; }
+
 struct KsLds {
     int RS, CSW;
     int off_v1, off_red, off_c, off_u, off_f, off_lr, total;
@@ -1387,9 +1434,12 @@ __global__ __launch_bounds__(kThreads) void pass_ks_kernel(PassArgs A) {
     // log rho into LDS; template scale from max |Re a|, |Im a| (a power of two, see the
     // storage-scaling note above)
     for (int i = tid; i < A.Wp; i += kThreads) lrs[i] = A.logrho32[i];
-    double amax = 0.0;
-    for (int r = tid; r < 2 * D; r += kThreads) amax = fmax(amax, fabs(A.a[r]));
-    amax = -block_min_d(-amax, (double *)(smem + LY.off_red), kThreads);
+    // a_t and the phase rows staged in LDS (the tile buffers' area, first copied into after the
+    // barrier that ends the template build)
+    const double amax = stage_a_e2(A, smem, (double *)rowf);
+    const float2 *as = (const float2 *)smem;
+    const float *es = (const float *)(smem + 8 * D);
+    const float rq = 1.0f / (float)A.Q;
     float sc = 1.0f, tsc = 1.0f;
     if (amax > 0.0) {
         const int e = ilogb(amax);
@@ -1405,15 +1455,15 @@ __global__ __launch_bounds__(kThreads) void pass_ks_kernel(PassArgs A) {
         const int d0 = ((wave * KSS + ks) * 32 + 8 * g) >> 1;
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-            const float *Ei = A.E2 + (int64_t)(nt * 16 + rl) * 2 * K;
+            const float *Ei = es + (nt * 16 + rl) * 2 * K;
             H hv[8], lv[8];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int d = d0 + e;
                 float tre = 0.f, tim = 0.f;
                 if (d < D) {
-                    const int k = d / A.Q;
-                    const float are = (float)A.a[2 * d], aim = (float)A.a[2 * d + 1];
+                    const int k = (int)(((float)d + 0.5f) * rq);      // d / Q
+                    const float are = as[d].x, aim = as[d].y;
                     const float er = Ei[k], ei = Ei[K + k];
                     tre = (are * er + aim * ei) * sc;
                     tim = (aim * er - are * ei) * sc;
@@ -1433,7 +1483,8 @@ __global__ __launch_bounds__(kThreads) void pass_ks_kernel(PassArgs A) {
     float ereg[KG];
 #pragma unroll
     for (int kk = 0; kk < KG; ++kk)
-        ereg[kk] = uok ? A.E2[(int64_t)(kk * 4 + g) * 2 * K + ucol] : 0.f;
+        ereg[kk] = uok ? es[(kk * 4 + g) * 2 * K + ucol] : 0.f;
+    __syncthreads();                                        // the staged tables are consumed
 
     const int64_t ntiles = (A.row_end - A.row_begin + BM - 1) / BM;
     PassAcc<DPT> acc;
@@ -1989,7 +2040,7 @@ __host__ __device__ inline KrLds kr_lds(int Dp) {
     l.off_w = l.off_red + 8 * 4 * kKrRedTile * 16;
     l.off_up = l.off_w + 2 * kKrBM * kKrWS;               // hi plane, then lo plane
     l.off_rs = l.off_up + 8 * 16 * kKrUS * 4;             // per-wave U blocks
-    l.off_lr = l.off_rs + kKrBufs * 64 * 4;               // row scales of the buffered tiles
+    l.off_lr = l.off_rs + 4 * 64 * 4;                     // row scales of four tiles
     l.off_wacc = l.off_lr + 64 * 4;                       // FP64 W_t sums: 16 row lanes x 64
     l.total = l.off_wacc + 16 * 64 * 8;
     return l;
@@ -2021,10 +2072,14 @@ __global__ __launch_bounds__(kThreads) void pass_kr_kernel(PassArgs A) {
     const bool deep = !(A.flags & (PF_STORE_LSE | PF_LOAD_LSE | PF_QUERY));
 
     for (int i = tid; i < 64; i += kThreads) lrs[i] = i < Wp ? A.logrho32[i] : -INFINITY;
-    // template scale from max |Re a|, |Im a| (a power of two, as in the other 16-bit passes)
-    double amax = 0.0;
-    for (int r = tid; r < 2 * D; r += kThreads) amax = fmax(amax, fabs(A.a[r]));
-    amax = -block_min_d(-amax, (double *)red, kThreads);
+    // a_t and the phase rows staged in LDS (where the third row buffer and the partials go,
+    // first written after the barrier that ends the prologue); the template scale from
+    // max |Re a|, |Im a| (a power of two, as in the other 16-bit passes)
+    uint8_t *stg = smem + 2 * BM * LY.RS;
+    const double amax = stage_a_e2(A, stg, (double *)(smem + LY.off_up));
+    const float2 *as = (const float2 *)stg;
+    const float *es = (const float *)(stg + 8 * D);
+    const int qs = __builtin_ctz(Q);                   // Q is a power of two
     float sc = 1.0f, tsc = 1.0f;
     if (amax > 0.0) {
         const int e = ilogb(amax);
@@ -2039,15 +2094,15 @@ __global__ __launch_bounds__(kThreads) void pass_kr_kernel(PassArgs A) {
         const int d0 = ((wave * KSS + ks) * 32 + 8 * g) >> 1;
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-            const float *Ei = A.E2 + (int64_t)(nt * 16 + rl) * 2 * K;
+            const float *Ei = es + (nt * 16 + rl) * 2 * K;
             H hv[8], lv[8];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int d = d0 + e;
                 float tre = 0.f, tim = 0.f;
                 if (d < D) {
-                    const int k = d / Q;
-                    const float are = (float)A.a[2 * d], aim = (float)A.a[2 * d + 1];
+                    const int k = d >> qs;
+                    const float are = as[d].x, aim = as[d].y;
                     const float er = Ei[k], ei = Ei[K + k];
                     tre = (are * er + aim * ei) * sc;
                     tim = (aim * er - are * ei) * sc;
@@ -2072,7 +2127,7 @@ __global__ __launch_bounds__(kThreads) void pass_kr_kernel(PassArgs A) {
         for (int t = 0; t < 8; ++t) {
             const int i = 32 * s + 8 * g + t, k = kbase + (rl >> 1);
             const float x = (i < Wp && (rl >> 1) < nk && k < K)
-                                ? A.E2[(int64_t)i * 2 * K + ((rl & 1) ? K : 0) + k] : 0.f;
+                                ? es[i * 2 * K + ((rl & 1) ? K : 0) + k] : 0.f;
             hv[t] = (H)x;
             lv[t] = (H)(x - (float)hv[t]);
         }
@@ -2087,14 +2142,14 @@ __global__ __launch_bounds__(kThreads) void pass_kr_kernel(PassArgs A) {
     const int64_t ntiles = (A.row_end - A.row_begin + BM - 1) / BM;
     const int64_t nmine = ntiles > (int64_t)blockIdx.x
                               ? (ntiles - 1 - (int64_t)blockIdx.x) / gridDim.x + 1 : 0;
-    // copy of this workgroup's j-th tile into buffer b: 32 chunks of 1 KiB (wave w: chunks w,
+    // copy of this workgroup's j-th tile into buffer j % 3: 32 chunks of 1 KiB (wave w: chunks w,
     // w + 8, w + 16, w + 24, i.e. rows w / 2 + 4 cc, half w % 2; rows past the end repeat the last
     // row, so every tile issues the same number of copies), and wave 0 the 64 row scales at and
-    // after the tile's first row
+    // after the tile's first row into slot j % 4
     const int64_t tstride = (int64_t)gridDim.x * BM;
-    auto issue = [&](int64_t j, int b) {
-        const int64_t r0 = A.row_begin + (int64_t)blockIdx.x * BM + j * tstride;
-        uint8_t *buf = smem + b * BM * LY.RS;
+    auto issue = [&](int j) {
+        const int64_t r0 = A.row_begin + (int64_t)blockIdx.x * BM + (int64_t)j * tstride;
+        uint8_t *buf = smem + (j % kKrBufs) * BM * LY.RS;
         const int rc = wave >> 1, kc = wave & 1;
         if (r0 + BM <= A.row_end) {
             const uint8_t *src = A.V + (r0 + rc) * A.rowbytes + kc * 1024 + lane * 16;
@@ -2113,7 +2168,7 @@ __global__ __launch_bounds__(kThreads) void pass_kr_kernel(PassArgs A) {
         }
         if (wave == 0) {
             const int64_t row = r0 + lane < A.row_end ? r0 + lane : A.row_end - 1;
-            dma_to_lds<4>(A.rowscale + row, rsb + b * 64);
+            dma_to_lds<4>(A.rowscale + row, rsb + (j & 3) * 64);
         }
     };
 
@@ -2155,35 +2210,18 @@ __global__ __launch_bounds__(kThreads) void pass_kr_kernel(PassArgs A) {
         s64[1] += (double)x1;
     };
 
-    if (nmine > 0) issue(0, 0);
-    if (nmine > 1) issue(1, 1);
-    int b = 0;                                   // buffer of tile j (tile j + 2 reuses j - 1's)
-    for (int64_t j = 0; j < nmine; ++j, b = b == kKrBufs - 1 ? 0 : b + 1) {
-        // this tile's copies have landed (the next tile's stay in flight) ...
-        if (deep && j + 1 < nmine) {
-            if (wave == 0) wait_vm<5>();
-            else wait_vm<4>();
-        } else {
-            wait_vm<0>();
-        }
-        // ... for every wave, and every wave is done with the previous tile's buffer
-        lds_barrier();
-        if (j + 2 < nmine) issue(j + 2, b == 0 ? kKrBufs - 1 : b - 1);
-        const uint8_t *Vs = smem + b * BM * LY.RS;
-        const float *rsv = rsb + b * 64;
-        const int64_t r0 = A.row_begin + (int64_t)blockIdx.x * BM + j * tstride;
-        const int rows = (int)((A.row_end - r0) < BM ? (A.row_end - r0) : BM);
-
-        // ---- a3: this wave's K-slice of the correlations
+    // ---- a3: this wave's K-slice of the correlations of the tile in buffer bt (formed
+    // transposed, template fragments as the A operand: lane 16 g + j ends with row j, columns
+    // 16 nt + 4 g .. 16 nt + 4 g + 3)
+    f32x4 c4[NT];
+    auto products = [&](int bt) {
+        const uint8_t *Vs = smem + bt * BM * LY.RS;
         u32x4 af[KSS];
 #pragma unroll
         for (int ks = 0; ks < KSS; ++ks)
             af[ks] = *(const u32x4 *)(Vs + rl * LY.RS + (wave * KSS + ks) * 64 + g * 16);
-        f32x4 c4[NT];
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) c4[nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
-        // (formed transposed, template fragments as the A operand: lane 16 g + j ends with row j,
-        // columns 16 nt + 4 g .. 16 nt + 4 g + 3)
 #pragma unroll
         for (int ks = 0; ks < KSS; ++ks) {
             const H8 bv = __builtin_bit_cast(H8, af[ks]);
@@ -2202,116 +2240,118 @@ __global__ __launch_bounds__(kThreads) void pass_kr_kernel(PassArgs A) {
                 }
             }
         }
+    };
+    auto put_red = [&]() {
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt)
             red[(wave * 4 + nt) * kKrRedTile + 17 * g + rl] = c4[nt];
-        lds_barrier();
+    };
 
-        // ---- a4: rows 2 wave, 2 wave + 1, 32 lanes per row, columns 2 x, 2 x + 1 per lane (x =
-        // lane % 32): the 8 partial sums in wave order, the log-sum-exp by 32-lane reductions
-        // (16-lane DPP rows, then the swizzle across the pair of rows), the posteriors written as
-        // 16-bit hi + lo planes
+    // ---- a4: rows 2 wave, 2 wave + 1 of tile j, 32 lanes per row, columns 2 x, 2 x + 1 per
+    // lane (x = lane % 32): the 8 partial sums in wave order, the log-sum-exp by 32-lane
+    // reductions (16-lane DPP rows, then the swizzle across the pair of rows), the posteriors
+    // written as 16-bit hi + lo planes
+    auto posteriors = [&](int64_t r0, int rows, const float *rsv) {
+        const int r = 2 * wave + (lane >> 5);
+        const bool rv = r < rows;
+        float l[2], e[2];
+        const float2 lr2 = *(const float2 *)(lrs + 2 * px);
+        const bool cok[2] = {2 * px < W, 2 * px + 1 < W};
         {
-            const int r = 2 * wave + (lane >> 5);
-            const bool rv = r < rows;
-            float l[2], e[2];
-            const float2 lr2 = *(const float2 *)(lrs + 2 * px);
-            const bool cok[2] = {2 * px < W, 2 * px + 1 < W};
-            {
-                const float *rp = (const float *)red + 4 * (pnt * kKrRedTile + 17 * pg + r) + 2 * ph;
-                float2 v = *(const float2 *)rp;
+            const float *rp = (const float *)red + 4 * (pnt * kKrRedTile + 17 * pg + r) + 2 * ph;
+            float2 v = *(const float2 *)rp;
 #pragma unroll
-                for (int w2 = 1; w2 < 8; ++w2) {
-                    const float2 t = *(const float2 *)(rp + 4 * (w2 * 4 * kKrRedTile));
-                    v.x += t.x;
-                    v.y += t.y;
+            for (int w2 = 1; w2 < 8; ++w2) {
+                const float2 t = *(const float2 *)(rp + 4 * (w2 * 4 * kKrRedTile));
+                v.x += t.x;
+                v.y += t.y;
+            }
+            const float rf = ct * rsv[r];
+            l[0] = (rv && cok[0]) ? v.x * rf + lr2.x : -INFINITY;
+            l[1] = (rv && cok[1]) ? v.y * rf + lr2.y : -INFINITY;
+        }
+        float lse;
+        if (A.flags & PF_LOAD_LSE) {
+            lse = rv ? (float)A.lse[r0 + r] : 0.f;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) e[q] = __expf(l[q] - lse);
+        } else {
+            float mx = row16_max(fmaxf(l[0], l[1]));
+            mx = fmaxf(mx, swz_xor16(mx));
+            if (!rv) mx = 0.f;                         // (an empty row: every l is -inf)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) e[q] = __expf(l[q] - mx);   // exp(-inf) = 0
+            float sx = row16_sum(e[0] + e[1]);
+            sx += swz_xor16(sx);
+            lse = mx + __logf(sx);
+            const float is = rv ? __builtin_amdgcn_rcpf(sx) : 0.f;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) e[q] *= is;
+        }
+        // e[] are the posteriors; sum_i w_i (l_i - log rho_i) for the per-row sum of w C
+        float wcs = (e[0] > 0.f ? e[0] * (l[0] - lr2.x) : 0.f) +
+                    (e[1] > 0.f ? e[1] * (l[1] - lr2.y) : 0.f);
+        wcs = row16_sum(wcs);
+        wcs += swz_xor16(wcs);
+        {
+            H hv[2], gv[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                hv[q] = (H)e[q];
+                gv[q] = (H)(e[q] - (float)hv[q]);
+                accW[q] += e[q];
+            }
+            *(uint32_t *)(wsh + r * kKrWS + 4 * px) = __builtin_bit_cast(uint32_t, hv);
+            *(uint32_t *)(wsh + BM * kKrWS + r * kKrWS + 4 * px) =
+                __builtin_bit_cast(uint32_t, gv);
+        }
+        if (rv && px == 0) {
+            acc_lse += (double)lse;
+            acc_wc += (double)wcs;
+            acc_rows += 1.0;
+            if (A.flags & PF_STORE_LSE) A.lse[r0 + r] = (double)lse;
+        }
+        if constexpr (query) {
+            // argmax (lowest column among equal maxima) and the gap to the runner-up
+            float m1 = row16_max(fmaxf(e[0], e[1]));
+            m1 = fmaxf(m1, swz_xor16(m1));
+            int idx = 1 << 30;
+#pragma unroll
+            for (int q = 1; q >= 0; --q)
+                if (cok[q] && e[q] == m1) idx = 2 * px + q;
+#pragma unroll
+            for (int o = 1; o < 32; o <<= 1) idx = min(idx, __shfl_xor(idx, o));
+            float m2 = 0.f;
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+                if (2 * px + q != idx) m2 = fmaxf(m2, e[q]);
+            m2 = row16_max(m2);
+            m2 = fmaxf(m2, swz_xor16(m2));
+            if (rv) {
+                const int64_t o = r0 + r - A.row_begin;
+                if (A.post)
+#pragma unroll
+                    for (int q = 0; q < 2; ++q)
+                        if (cok[q]) A.post[o * W + 2 * px + q] = e[q];
+                if (px == 0) {
+                    if (A.argmax) A.argmax[o] = idx;
+                    if (A.margin) A.margin[o] = m1 - m2;
                 }
-                const float rf = ct * rsv[r];
-                l[0] = (rv && cok[0]) ? v.x * rf + lr2.x : -INFINITY;
-                l[1] = (rv && cok[1]) ? v.y * rf + lr2.y : -INFINITY;
-            }
-            float lse;
-            if (A.flags & PF_LOAD_LSE) {
-                lse = rv ? (float)A.lse[r0 + r] : 0.f;
-#pragma unroll
-                for (int q = 0; q < 2; ++q) e[q] = __expf(l[q] - lse);
-            } else {
-                float mx = row16_max(fmaxf(l[0], l[1]));
-                mx = fmaxf(mx, swz_xor16(mx));
-                if (!rv) mx = 0.f;                         // (an empty row: every l is -inf)
-#pragma unroll
-                for (int q = 0; q < 2; ++q) e[q] = __expf(l[q] - mx);   // exp(-inf) = 0
-                float sx = row16_sum(e[0] + e[1]);
-                sx += swz_xor16(sx);
-                lse = mx + __logf(sx);
-                const float is = rv ? __builtin_amdgcn_rcpf(sx) : 0.f;
-#pragma unroll
-                for (int q = 0; q < 2; ++q) e[q] *= is;
-            }
-            // e[] are the posteriors; sum_i w_i (l_i - log rho_i) for the per-row sum of w C
-            float wcs = (e[0] > 0.f ? e[0] * (l[0] - lr2.x) : 0.f) +
-                        (e[1] > 0.f ? e[1] * (l[1] - lr2.y) : 0.f);
-            wcs = row16_sum(wcs);
-            wcs += swz_xor16(wcs);
-            {
-                H hv[2], gv[2];
-#pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    hv[q] = (H)e[q];
-                    gv[q] = (H)(e[q] - (float)hv[q]);
-                    accW[q] += e[q];
-                }
-                *(uint32_t *)(wsh + r * kKrWS + 4 * px) = __builtin_bit_cast(uint32_t, hv);
-                *(uint32_t *)(wsh + BM * kKrWS + r * kKrWS + 4 * px) =
-                    __builtin_bit_cast(uint32_t, gv);
-            }
-            if (rv && px == 0) {
-                acc_lse += (double)lse;
-                acc_wc += (double)wcs;
-                acc_rows += 1.0;
-                if (A.flags & PF_STORE_LSE) A.lse[r0 + r] = (double)lse;
-            }
-            if constexpr (query) {
-                // argmax (lowest column among equal maxima) and the gap to the runner-up
-                float m1 = row16_max(fmaxf(e[0], e[1]));
-                m1 = fmaxf(m1, swz_xor16(m1));
-                int idx = 1 << 30;
-#pragma unroll
-                for (int q = 1; q >= 0; --q)
-                    if (cok[q] && e[q] == m1) idx = 2 * px + q;
-#pragma unroll
-                for (int o = 1; o < 32; o <<= 1) idx = min(idx, __shfl_xor(idx, o));
-                float m2 = 0.f;
-#pragma unroll
-                for (int q = 0; q < 2; ++q)
-                    if (2 * px + q != idx) m2 = fmaxf(m2, e[q]);
-                m2 = row16_max(m2);
-                m2 = fmaxf(m2, swz_xor16(m2));
-                if (rv) {
-                    const int64_t o = r0 + r - A.row_begin;
-                    if (A.post)
-#pragma unroll
-                        for (int q = 0; q < 2; ++q)
-                            if (cok[q]) A.post[o * W + 2 * px + q] = e[q];
-                    if (px == 0) {
-                        if (A.argmax) A.argmax[o] = idx;
-                        if (A.margin) A.margin[o] = m1 - m2;
-                    }
-                }
-            }
-            if (++nfw == kKrFlush) {                       // W_t sums: FP32 over 16 tiles
-#pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    wacc[q] += (double)accW[q];
-                    accW[q] = 0.f;
-                }
-                nfw = 0;
             }
         }
-        if (!accm) continue;
-        lds_barrier();
+        if (++nfw == kKrFlush) {                       // W_t sums: FP32 over 16 tiles
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                wacc[q] += (double)accW[q];
+                accW[q] = 0.f;
+            }
+            nfw = 0;
+        }
+    };
 
-        // ---- a5: U^T for this wave's frequencies, then the M-step on the wave's fragments
+    // ---- a5: U^T for this wave's frequencies, then the M-step on the wave's fragments of the
+    // tile (rows Vs in LDS)
+    auto mstep = [&](int rows, const float *rsv, const uint8_t *Vs) {
         f32x4 u4 = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
@@ -2333,7 +2373,7 @@ __global__ __launch_bounds__(kThreads) void pass_kr_kernel(PassArgs A) {
 #pragma unroll
         for (int ks = 0; ks < KSS; ++ks) {
             const float2 U = *(const float2 *)(up + rl * kKrUS + um[ks]);
-            const H8 v8 = __builtin_bit_cast(H8, af[ks]);
+            const H8 v8 = *(const H8 *)(Vs + rl * LY.RS + (wave * KSS + ks) * 64 + g * 16);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const float vr = (float)v8[2 * e], vi = (float)v8[2 * e + 1];
@@ -2345,6 +2385,54 @@ __global__ __launch_bounds__(kThreads) void pass_kr_kernel(PassArgs A) {
             fold();
             nfl = 0;
         }
+    };
+
+    // Software pipeline over this workgroup's tiles, two barriers per tile j: after the first
+    // (tile j's partial correlations are in LDS) every wave forms its rows' posteriors of tile
+    // j; after the second, it runs the products of tile j + 1, puts their partials in LDS, and
+    // runs U and the M-step of tile j on its fragments of tile j, read again from LDS (a wave
+    // whose products are done goes on to the M-step's vector work while the SIMD's other wave
+    // still has products in the matrix core).  Tile t's rows sit in buffer t % 3 (copied during
+    // tile t - 2, read by the products during tile t - 1 and by the M-step during tile t), its
+    // row scales in slot t % 4.
+    const int nm = (int)nmine;
+    if (nm > 0) issue(0);
+    if (nm > 1) issue(1);
+    if (nm > 0) {                                // tile 0's products
+        if (deep && nm > 1) {
+            if (wave == 0) wait_vm<5>();
+            else wait_vm<4>();
+        } else {
+            wait_vm<0>();
+        }
+        lds_barrier();
+        products(0);
+        put_red();
+    }
+    for (int j = 0, bc = 0; j < nm; ++j, bc = bc == kKrBufs - 1 ? 0 : bc + 1) {
+        // tile j's partials are in LDS, and every wave is done with tile j - 1's rows and row
+        // scales (whose buffer and slot tile j + 2 takes)
+        lds_barrier();
+        if (j + 2 < nm) issue(j + 2);
+        const int64_t r0 = A.row_begin + (int64_t)blockIdx.x * BM + (int64_t)j * tstride;
+        const int rows = (int)((A.row_end - r0) < BM ? (A.row_end - r0) : BM);
+        const float *rsv = rsb + (j & 3) * 64;
+        posteriors(r0, rows, rsv);
+        // tile j + 1's copies have landed (tile j + 2's stay in flight) ...
+        if (deep && j + 2 < nm) {
+            if (wave == 0) wait_vm<5>();
+            else wait_vm<4>();
+        } else {
+            wait_vm<0>();
+        }
+        // ... for every wave; every wave is done reading tile j's partials, and tile j's
+        // posteriors are in LDS
+        lds_barrier();
+        if (j + 1 < nm) {
+            products(bc == kKrBufs - 1 ? 0 : bc + 1);
+            put_red();
+        }
+        if (accm) mstep(rows, rsv, smem + bc * BM * LY.RS);
     }
     fold();
 #pragma unroll
@@ -4432,8 +4520,11 @@ static pass_fn find_ks(int prec, int BM, int NT, int KSS, int QRY = 0) {
 bool ks_plan(int prec, int Dp, int Wp, int K, int *BM, int *NT, int *KSS) {
     const int nt = Wp / 16, kss = Dp / 256;
     if (Dp % 256 != 0 || 2 * K > 16 * (kThreads / 64)) return false;   // one U tile per wave
+    // a_t and the phase rows are staged below the row factors at the start of a launch
+    if (Dp / 2 > kStageA * kThreads || Wp * 2 * K > kStageE * kThreads) return false;
     for (int bm : {32, 16})
-        if (find_ks(prec, bm, nt, kss)) {
+        if (find_ks(prec, bm, nt, kss) &&
+            stage_a_e2_bytes(Dp / 2, Wp, K) <= ks_lds(prec, bm, nt, K, Dp, Wp).off_f) {
             *BM = bm;
             *NT = nt;
             *KSS = kss;
