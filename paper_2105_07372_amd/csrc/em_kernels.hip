@@ -1231,6 +1231,35 @@ __device__ double stage_a_e2(const PassArgs &A, uint8_t *st, double *sh8) {
 }
 __host__ __device__ inline int stage_a_e2_bytes(int D, int Wp, int K) { return 8 * D + 8 * Wp * K; }
 
+// One B fragment of the rotated template from the staged tables: entries d0 .. d0 + 3 at window
+// column i (phase row Ei), T = (Re, Im)(a_d conj(exp(+i k_d theta_i))) sc with k_d = d / Q
+// (rq = 1 / Q; (d + 1/2) / Q sits at least 1 / (2 Q) from an integer, far beyond the rounding of
+// the product), split into 16-bit hi + lo; entries at or past D are zero.  Branch-free: the reads
+// are clamped into the tables and the entries selected afterwards, so that the reads of a whole
+// template slice can be in flight together.
+template <typename H>
+__device__ __forceinline__ void tpl_frag(const float2 *as, const float *Ei, int d0, int D, int K,
+                                         float rq, float sc, u32x4 &hi, u32x4 &lo) {
+    H hv[8], lv[8];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int d = d0 + e;
+        const bool ok = d < D;
+        const int dc = ok ? d : D - 1;
+        const int k = (int)(((float)dc + 0.5f) * rq);
+        const float2 a = as[dc];
+        const float er = Ei[k], ei = Ei[K + k];
+        const float tre = ok ? (a.x * er + a.y * ei) * sc : 0.f;
+        const float tim = ok ? (a.y * er - a.x * ei) * sc : 0.f;
+        hv[2 * e] = (H)tre;
+        hv[2 * e + 1] = (H)tim;
+        lv[2 * e] = (H)(tre - (float)hv[2 * e]);
+        lv[2 * e + 1] = (H)(tim - (float)hv[2 * e + 1]);
+    }
+    hi = __builtin_bit_cast(u32x4, hv);
+    lo = __builtin_bit_cast(u32x4, lv);
+}
+
 struct KsLds {
     int RS, CSW;
     int off_v1, off_red, off_c, off_u, off_f, off_lr, total;
@@ -1454,28 +1483,9 @@ __global__ __launch_bounds__(kThreads) void pass_ks_kernel(PassArgs A) {
     for (int ks = 0; ks < KSS; ++ks) {
         const int d0 = ((wave * KSS + ks) * 32 + 8 * g) >> 1;
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            const float *Ei = es + (nt * 16 + rl) * 2 * K;
-            H hv[8], lv[8];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int d = d0 + e;
-                float tre = 0.f, tim = 0.f;
-                if (d < D) {
-                    const int k = (int)(((float)d + 0.5f) * rq);      // d / Q
-                    const float are = as[d].x, aim = as[d].y;
-                    const float er = Ei[k], ei = Ei[K + k];
-                    tre = (are * er + aim * ei) * sc;
-                    tim = (aim * er - are * ei) * sc;
-                }
-                hv[2 * e] = (H)tre;
-                hv[2 * e + 1] = (H)tim;
-                lv[2 * e] = (H)(tre - (float)hv[2 * e]);
-                lv[2 * e + 1] = (H)(tim - (float)hv[2 * e + 1]);
-            }
-            treg[ks][nt][0] = __builtin_bit_cast(u32x4, hv);
-            treg[ks][nt][1] = __builtin_bit_cast(u32x4, lv);
-        }
+        for (int nt = 0; nt < NT; ++nt)
+            tpl_frag<H>(as, es + (nt * 16 + rl) * 2 * K, d0, D, K, rq, sc, treg[ks][nt][0],
+                        treg[ks][nt][1]);
     }
     // B fragments of U = w [Re E | Im E] for this wave's 16-column tile of U
     const int ucol = wave * 16 + rl;
@@ -1483,7 +1493,7 @@ __global__ __launch_bounds__(kThreads) void pass_ks_kernel(PassArgs A) {
     float ereg[KG];
 #pragma unroll
     for (int kk = 0; kk < KG; ++kk)
-        ereg[kk] = uok ? es[(kk * 4 + g) * 2 * K + ucol] : 0.f;
+        ereg[kk] = uok ? es[uok ? (kk * 4 + g) * 2 * K + ucol : 0] : 0.f;
     __syncthreads();                                        // the staged tables are consumed
 
     const int64_t ntiles = (A.row_end - A.row_begin + BM - 1) / BM;
@@ -2089,24 +2099,24 @@ __global__ __launch_bounds__(kThreads) void pass_kr_kernel(PassArgs A) {
     // this wave's template slice: T[r][i] = (Re, Im)(a_d exp(-i k_d theta_i)) sc, d = r / 2,
     // B fragments (column i = 16 nt + lane % 16, reals 8 g .. 8 g + 7 of the k-step), hi + lo
     u32x4 treg[KSS][NT][2];
+    // (the lane's four entries of a k-step share one frequency, Q >= 8; sc, a power of two, is
+    // applied to a first, which leaves every product as it would be scaled afterwards)
 #pragma unroll
     for (int ks = 0; ks < KSS; ++ks) {
-        const int d0 = ((wave * KSS + ks) * 32 + 8 * g) >> 1;
+        const int d0 = ((wave * KSS + ks) * 32 + 8 * g) >> 1;       // a multiple of 4, < D
+        const int k = d0 >> qs;
+        const float4 a01 = *(const float4 *)(as + d0), a23 = *(const float4 *)(as + d0 + 2);
+        const float ar[4] = {a01.x * sc, a01.z * sc, a23.x * sc, a23.z * sc};
+        const float ai[4] = {a01.y * sc, a01.w * sc, a23.y * sc, a23.w * sc};
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
             const float *Ei = es + (nt * 16 + rl) * 2 * K;
+            const float er = Ei[k], ei = Ei[K + k];
             H hv[8], lv[8];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int d = d0 + e;
-                float tre = 0.f, tim = 0.f;
-                if (d < D) {
-                    const int k = d >> qs;
-                    const float are = as[d].x, aim = as[d].y;
-                    const float er = Ei[k], ei = Ei[K + k];
-                    tre = (are * er + aim * ei) * sc;
-                    tim = (aim * er - are * ei) * sc;
-                }
+                const float tre = ar[e] * er + ai[e] * ei;
+                const float tim = ai[e] * er - ar[e] * ei;
                 hv[2 * e] = (H)tre;
                 hv[2 * e + 1] = (H)tim;
                 lv[2 * e] = (H)(tre - (float)hv[2 * e]);
@@ -2126,8 +2136,9 @@ __global__ __launch_bounds__(kThreads) void pass_kr_kernel(PassArgs A) {
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
             const int i = 32 * s + 8 * g + t, k = kbase + (rl >> 1);
-            const float x = (i < Wp && (rl >> 1) < nk && k < K)
-                                ? es[i * 2 * K + ((rl & 1) ? K : 0) + k] : 0.f;
+            const bool ok = i < Wp && (rl >> 1) < nk && k < K;
+            const float v = es[(ok ? i * 2 * K + ((rl & 1) ? K : 0) + k : 0)];
+            const float x = ok ? v : 0.f;
             hv[t] = (H)x;
             lv[t] = (H)(x - (float)hv[t]);
         }
@@ -3602,17 +3613,37 @@ __global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
     float2 *as = (float2 *)(smem + LY.off_a);
 
     // tables: ct / st entry [m][k] (row stride TS) = cos / sin (kbar_k theta_m) (zero past M
-    // and K; sines zero where the offset is its own mirror)
-    for (int x = tid; x < MT * 16 * TS; x += kThreads) {
-        const int m = x / TS, k = x % TS;
-        float cv = 0.f, sv = 0.f;
-        if (m < M && k < K) {
-            const float *e = A.E2 + (int64_t)fs_plus(m, L, lo) * 2 * K;
-            cv = e[k];
-            sv = fs_mirror(m, L, lo, W) >= 0 ? e[K + k] : 0.f;
+    // and K; sines zero where the offset is its own mirror).  Wave w fills rows w, w + 8, ...,
+    // lane l entry k = l (K <= 64; entries 64 .. TS - 1 are zero); a row's window indices are
+    // uniform over the wave, and eight rows' reads are issued before any is stored.
+    static_assert(TS - 64 <= 64, "one extra lane pass of zeros");
+    for (int m0 = wave; m0 < MT * 16; m0 += 64) {
+        float cv[8], sv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int m = m0 + 8 * u;
+            const bool ok = m < M && lane < K;
+            const int ip = m < M ? fs_plus(m, L, lo) : 0;
+            const bool mir = m < M && fs_mirror(m, L, lo, W) >= 0;
+            const float *e = A.E2 + (int64_t)ip * 2 * K;
+            const float c0 = e[ok ? lane : 0], s0 = e[ok ? K + lane : 0];
+            cv[u] = ok ? c0 : 0.f;
+            sv[u] = ok && mir ? s0 : 0.f;
         }
-        ct[x] = cv;
-        st[x] = sv;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int m = m0 + 8 * u;
+            if (m < MT * 16) {
+                if (lane < TS) {
+                    ct[m * TS + lane] = cv[u];
+                    st[m * TS + lane] = sv[u];
+                }
+                if (64 + lane < TS) {
+                    ct[m * TS + 64 + lane] = 0.f;
+                    st[m * TS + 64 + lane] = 0.f;
+                }
+            }
+        }
     }
     for (int m = tid; m < MT * 16; m += kThreads) {
         float p = -INFINITY, q = -INFINITY;
@@ -3630,8 +3661,20 @@ __global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
     for (int x = tid; x < 8 * 16; x += kThreads) xs[x] = make_float2(-INFINITY, 0.f);
     for (int x = tid; x < 8 * KR * US; x += kThreads) up[x] = make_float2(0.f, 0.f);
     for (int i = tid; i < Wp; i += kThreads) wt64[i] = 0.0;
-    for (int d = tid; d < D; d += kThreads)
-        as[(d % EPL) * NVL + d / EPL] = make_float2((float)A.a[2 * d], (float)A.a[2 * d + 1]);
+    {
+        constexpr int NA = NVL * EPL / kThreads;        // D <= NVL EPL entries, read together
+        double2 av[NA];
+#pragma unroll
+        for (int c = 0; c < NA; ++c) {
+            const int d = tid + c * kThreads;
+            av[c] = d < D ? ((const double2 *)A.a)[d] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int c = 0; c < NA; ++c) {
+            const int d = tid + c * kThreads;
+            if (d < D) as[(d % EPL) * NVL + d / EPL] = make_float2((float)av[c].x, (float)av[c].y);
+        }
+    }
     if constexpr (HR)
         for (int d = tid; d < D; d += kThreads) ((double2 *)Sw)[d] = make_double2(0.0, 0.0);
     __syncthreads();
