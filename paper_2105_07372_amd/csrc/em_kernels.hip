@@ -1260,6 +1260,26 @@ __device__ __forceinline__ void tpl_frag(const float2 *as, const float *Ei, int 
     lo = __builtin_bit_cast(u32x4, lv);
 }
 
+// The same fragment when the four entries share one frequency (Q % 4 == 0): ar, ai are
+// Re, Im a_d of the four entries already multiplied by sc (a power of two, so every product is
+// what scaling it afterwards gives), er, ei the phase at their frequency.
+template <typename H>
+__device__ __forceinline__ void tpl_frag4(const float ar[4], const float ai[4], float er, float ei,
+                                          u32x4 &hi, u32x4 &lo) {
+    H hv[8], lv[8];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const float tre = ar[e] * er + ai[e] * ei;
+        const float tim = ai[e] * er - ar[e] * ei;
+        hv[2 * e] = (H)tre;
+        hv[2 * e + 1] = (H)tim;
+        lv[2 * e] = (H)(tre - (float)hv[2 * e]);
+        lv[2 * e + 1] = (H)(tim - (float)hv[2 * e + 1]);
+    }
+    hi = __builtin_bit_cast(u32x4, hv);
+    lo = __builtin_bit_cast(u32x4, lv);
+}
+
 struct KsLds {
     int RS, CSW;
     int off_v1, off_red, off_c, off_u, off_f, off_lr, total;
@@ -1481,11 +1501,26 @@ __global__ __launch_bounds__(kThreads) void pass_ks_kernel(PassArgs A) {
     u32x4 treg[KSS][NT][2];
 #pragma unroll
     for (int ks = 0; ks < KSS; ++ks) {
-        const int d0 = ((wave * KSS + ks) * 32 + 8 * g) >> 1;
+        const int d0 = ((wave * KSS + ks) * 32 + 8 * g) >> 1;        // a multiple of 4
+        if (A.Q % 4 == 0 && D % 4 == 0) {           // the four entries share k and validity
+            const bool ok = d0 < D;
+            const int k = ok ? (int)(((float)d0 + 0.5f) * rq) : 0;
+            const float4 a01 = *(const float4 *)(as + (ok ? d0 : 0));
+            const float4 a23 = *(const float4 *)(as + (ok ? d0 + 2 : 0));
+            const float f = ok ? sc : 0.f;
+            const float ar[4] = {a01.x * f, a01.z * f, a23.x * f, a23.z * f};
+            const float ai[4] = {a01.y * f, a01.w * f, a23.y * f, a23.w * f};
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-            tpl_frag<H>(as, es + (nt * 16 + rl) * 2 * K, d0, D, K, rq, sc, treg[ks][nt][0],
-                        treg[ks][nt][1]);
+            for (int nt = 0; nt < NT; ++nt) {
+                const float *Ei = es + (nt * 16 + rl) * 2 * K;
+                tpl_frag4<H>(ar, ai, Ei[k], Ei[K + k], treg[ks][nt][0], treg[ks][nt][1]);
+            }
+        } else {
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+                tpl_frag<H>(as, es + (nt * 16 + rl) * 2 * K, d0, D, K, rq, sc, treg[ks][nt][0],
+                            treg[ks][nt][1]);
+        }
     }
     // B fragments of U = w [Re E | Im E] for this wave's 16-column tile of U
     const int ucol = wave * 16 + rl;
@@ -2111,19 +2146,7 @@ __global__ __launch_bounds__(kThreads) void pass_kr_kernel(PassArgs A) {
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
             const float *Ei = es + (nt * 16 + rl) * 2 * K;
-            const float er = Ei[k], ei = Ei[K + k];
-            H hv[8], lv[8];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const float tre = ar[e] * er + ai[e] * ei;
-                const float tim = ai[e] * er - ar[e] * ei;
-                hv[2 * e] = (H)tre;
-                hv[2 * e + 1] = (H)tim;
-                lv[2 * e] = (H)(tre - (float)hv[2 * e]);
-                lv[2 * e + 1] = (H)(tim - (float)hv[2 * e + 1]);
-            }
-            treg[ks][nt][0] = __builtin_bit_cast(u32x4, hv);
-            treg[ks][nt][1] = __builtin_bit_cast(u32x4, lv);
+            tpl_frag4<H>(ar, ai, Ei[k], Ei[K + k], treg[ks][nt][0], treg[ks][nt][1]);
         }
     }
     // A fragments of U^T = E'^T w^T: row m of E'^T is Re (m even) or Im (m odd) of
@@ -3581,6 +3604,16 @@ __host__ __device__ inline int fs_mirror(int m, int L, int lo, int W) {
     const int i = fs_mod(-m - lo, L);
     return (i < W && i != fs_plus(m, L, lo)) ? i : -1;
 }
+// The same for 0 <= m < L and 0 <= lo < L without a division (the kernels' tables)
+__device__ __forceinline__ int fs_plus_d(int m, int L, int lo) {
+    const int x = m - lo;
+    return x < 0 ? x + L : x;
+}
+__device__ __forceinline__ int fs_mirror_d(int m, int L, int lo, int W) {
+    int i = L - m - lo;                            // in (-L, L]
+    i = i < 0 ? i + L : (i == L ? 0 : i);
+    return (i < W && i != fs_plus_d(m, L, lo)) ? i : -1;
+}
 
 template <int P, int MTW, int E>
 __global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
@@ -3623,8 +3656,8 @@ __global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
         for (int u = 0; u < 8; ++u) {
             const int m = m0 + 8 * u;
             const bool ok = m < M && lane < K;
-            const int ip = m < M ? fs_plus(m, L, lo) : 0;
-            const bool mir = m < M && fs_mirror(m, L, lo, W) >= 0;
+            const int ip = m < M ? fs_plus_d(m, L, lo) : 0;
+            const bool mir = m < M && fs_mirror_d(m, L, lo, W) >= 0;
             const float *e = A.E2 + (int64_t)ip * 2 * K;
             const float c0 = e[ok ? lane : 0], s0 = e[ok ? K + lane : 0];
             cv[u] = ok ? c0 : 0.f;
@@ -3648,8 +3681,8 @@ __global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
     for (int m = tid; m < MT * 16; m += kThreads) {
         float p = -INFINITY, q = -INFINITY;
         if (m < M) {
-            p = A.logrho32[fs_plus(m, L, lo)];
-            const int im = fs_mirror(m, L, lo, W);
+            p = A.logrho32[fs_plus_d(m, L, lo)];
+            const int im = fs_mirror_d(m, L, lo, W);
             if (im >= 0) q = A.logrho32[im];
         }
         lrp[m] = p;
@@ -3765,8 +3798,8 @@ __global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
                 const float sp = row16_sum(wsp[t][q]), sm = row16_sum(wsm[t][q]);
                 const int m = 16 * mt + 4 * g + q;
                 if (c16 == 0 && m < M) {
-                    wt64[fs_plus(m, L, lo)] += (double)sp;
-                    const int im = fs_mirror(m, L, lo, W);
+                    wt64[fs_plus_d(m, L, lo)] += (double)sp;
+                    const int im = fs_mirror_d(m, L, lo, W);
                     if (im >= 0) wt64[im] += (double)sm;
                 }
                 wsp[t][q] = wsm[t][q] = 0.f;
