@@ -993,6 +993,34 @@ __device__ __forceinline__ void tile_post(const PassArgs &A, const PassLds &LY, 
 }
 
 // Per-workgroup partials: S (2D), W (Wp), sum lse', sum w*C, rows, 0.
+// The per-workgroup scalars of a pass (sum of per-row log-sum-exps, sum of w C, rows) summed in a
+// fixed order (a 64-lane butterfly, which leaves every lane with the same sum, then the waves in
+// order) and stored at out[0 .. 3] (the w C sum divided by coef, then a zero).  sh: 3 doubles per
+// wave of LDS that no wave still uses.
+__device__ __forceinline__ void put_pass_scalars(double *out, double lse, double wc, double rows,
+                                                 double coef, double *sh) {
+    double v[3] = {lse, wc, rows};
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) v[q] += __shfl_xor(v[q], o);
+    const int t = threadIdx.x;
+    if ((t & 63) == 0)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) sh[(t >> 6) * 3 + q] = v[q];
+    __syncthreads();
+    if (t == 0) {
+        double r[3] = {sh[0], sh[1], sh[2]};
+        for (int w = 1; w < kThreads / 64; ++w)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) r[q] += sh[w * 3 + q];
+        out[0] = r[0];
+        out[1] = r[1] / coef;
+        out[2] = r[2];
+        out[3] = 0.0;
+    }
+}
+
 template <int DPT>
 __device__ __forceinline__ void write_partials(const PassArgs &A, PassAcc<DPT> &acc,
                                                uint8_t *smem) {
@@ -1015,16 +1043,8 @@ __device__ __forceinline__ void write_partials(const PassArgs &A, PassAcc<DPT> &
         for (int i = tid; i < 2 * A.D + A.Wp; i += kThreads) Pp[i] = 0.0;
     }
     __syncthreads();
-    double *sh = (double *)smem;
-    const double s_lse = block_sum_d(acc.lse, sh, kThreads);
-    const double s_wc = block_sum_d(acc.wc, sh, kThreads);
-    const double s_rows = block_sum_d(acc.rows, sh, kThreads);
-    if (tid == 0) {
-        Pp[2 * A.D + A.Wp] = s_lse;
-        Pp[2 * A.D + A.Wp + 1] = s_wc / A.coef;         // sum_j sum_i w_ji C_ji
-        Pp[2 * A.D + A.Wp + 2] = s_rows;
-        Pp[2 * A.D + A.Wp + 3] = 0.0;
-    }
+    // (sum_j lse'_j, sum_j sum_i w_ji C_ji, rows)
+    put_pass_scalars(Pp + 2 * A.D + A.Wp, acc.lse, acc.wc, acc.rows, A.coef, (double *)smem);
 }
 
 // Global-to-LDS copy of BYTES (16 or 4) per lane: lane l's bytes land at lds_dst + BYTES l (lds_dst
@@ -2491,16 +2511,7 @@ __global__ __launch_bounds__(kThreads) void pass_kr_kernel(PassArgs A) {
             Pp[2 * D + tid] = accm ? t : 0.0;
         }
         __syncthreads();
-        double *sh = (double *)smem;
-        const double s_lse = block_sum_d(acc_lse, sh, kThreads);
-        const double s_wc = block_sum_d(acc_wc, sh, kThreads);
-        const double s_rows = block_sum_d(acc_rows, sh, kThreads);
-        if (tid == 0) {
-            Pp[2 * D + Wp] = s_lse;
-            Pp[2 * D + Wp + 1] = s_wc / A.coef;
-            Pp[2 * D + Wp + 2] = s_rows;
-            Pp[2 * D + Wp + 3] = 0.0;
-        }
+        put_pass_scalars(Pp + 2 * D + Wp, acc_lse, acc_wc, acc_rows, A.coef, (double *)smem);
     }
 }
 
@@ -2854,16 +2865,7 @@ __global__ __launch_bounds__(kThreads) void pass_gm_kernel(PassArgs A) {
         }
         if (tid < Wp) Pp[2 * D + tid] = accm ? Wacc : 0.0;
         __syncthreads();
-        double *sh = (double *)smem;
-        const double s_lse = block_sum_d(acc_lse, sh, kThreads);
-        const double s_wc = block_sum_d(acc_wc, sh, kThreads);
-        const double s_rows = block_sum_d(acc_rows, sh, kThreads);
-        if (tid == 0) {
-            Pp[2 * D + Wp] = s_lse;
-            Pp[2 * D + Wp + 1] = s_wc / A.coef;
-            Pp[2 * D + Wp + 2] = s_rows;
-            Pp[2 * D + Wp + 3] = 0.0;
-        }
+        put_pass_scalars(Pp + 2 * D + Wp, acc_lse, acc_wc, acc_rows, A.coef, (double *)smem);
     }
 }
 
@@ -3648,12 +3650,14 @@ __global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
     // tables: ct / st entry [m][k] (row stride TS) = cos / sin (kbar_k theta_m) (zero past M
     // and K; sines zero where the offset is its own mirror).  Wave w fills rows w, w + 8, ...,
     // lane l entry k = l (K <= 64; entries 64 .. TS - 1 are zero); a row's window indices are
-    // uniform over the wave, and eight rows' reads are issued before any is stored.
+    // uniform over the wave, and 24 rows' reads (all of a wave's rows up to M = 192) are issued
+    // before any is stored.
     static_assert(TS - 64 <= 64, "one extra lane pass of zeros");
-    for (int m0 = wave; m0 < MT * 16; m0 += 64) {
-        float cv[8], sv[8];
+    constexpr int RU = 24;
+    for (int m0 = wave; m0 < MT * 16; m0 += 8 * RU) {
+        float cv[RU], sv[RU];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < RU; ++u) {
             const int m = m0 + 8 * u;
             const bool ok = m < M && lane < K;
             const int ip = m < M ? fs_plus_d(m, L, lo) : 0;
@@ -3664,7 +3668,7 @@ __global__ __launch_bounds__(kThreads) void pass_fs_kernel(PassArgs A) {
             sv[u] = ok && mir ? s0 : 0.f;
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < RU; ++u) {
             const int m = m0 + 8 * u;
             if (m < MT * 16) {
                 if (lane < TS) {
@@ -4208,10 +4212,14 @@ __device__ void finalize_body(const FinArgs &F) {
             if (F.gai) gv[c] = F.gai[d];
         }
     }
+    // rho entries i = tw, tw + kFinThreads, ... with tw = (t + 128) mod kFinThreads: windows up
+    // to 128 land on the last two waves, which have no rotation of the stopping metric (L <= 384),
+    // so that their logarithms run beside it
+    const int tw = (t + 128) % kFinThreads;
     double wt[WPF], rb[WPF], ri[WPF];
 #pragma unroll
     for (int c = 0; c < WPF; ++c) {
-        const int i = t + c * kFinThreads;
+        const int i = tw + c * kFinThreads;
         wt[c] = rb[c] = 0.0;
         ri[c] = 1.0;
         if (i < W) {
@@ -4226,10 +4234,11 @@ __device__ void finalize_body(const FinArgs &F) {
     // ||a_t||^2, MAP prior terms, a_{t+1}, ||a_{t+1}||^2, ||a_{t+1} - a_t||^2, the rho normaliser
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     double2 an[DPF];
+    const double rden0 = 1.0 / N;                 // (the same as below with no prior on a)
 #pragma unroll
     for (int c = 0; c < DPF; ++c) {
         const int d = t + c * kFinThreads;
-        const double rden = 1.0 / (N + F.sigma2 * gv[c]);
+        const double rden = F.gai ? 1.0 / (N + F.sigma2 * gv[c]) : rden0;
         an[c] = make_double2(sd[c].x * rden, sd[c].y * rden);
         if (d < D) {
             const double ar = at[c].x, ai = at[c].y;
@@ -4243,7 +4252,7 @@ __device__ void finalize_body(const FinArgs &F) {
     }
 #pragma unroll
     for (int c = 0; c < WPF; ++c) {
-        if (t + c * kFinThreads >= W) continue;
+        if (tw + c * kFinThreads >= W) continue;
         if (F.gamma != 0.0 && rb[c] > 0.0) v[1] += F.gamma * rb[c] * log(ri[c]);
         v[4] += wt[c] + F.gamma * rb[c];
     }
@@ -4275,7 +4284,7 @@ __device__ void finalize_body(const FinArgs &F) {
     double ent = 0.0;
 #pragma unroll
     for (int c = 0; c < WPF; ++c) {
-        const int i = t + c * kFinThreads;
+        const int i = tw + c * kFinThreads;
         if (i >= F.Wp) continue;
         const double r = i < W ? (F.update_rho ? (wt[c] + F.gamma * rb[c]) * rtot : ri[c]) : 0.0;
         const double l = r > 0.0 ? log(r) : -INFINITY;
