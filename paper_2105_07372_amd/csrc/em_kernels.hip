@@ -1158,12 +1158,24 @@ __global__ __launch_bounds__(kThreads) void pass_kernel(PassArgs A) {
 
         // ---- a3: correlations C and log-weights l' = coef * C + log rho  -> Cs
         if constexpr (P == P_F64) {
+            // (the template column is read from global memory 16 reals at a time, all 16 reads
+            // issued before the products, which run in four chains added at the end)
             const double *Td = (const double *)A.Thi;
             for (int o = tid; o < BM * A.Wp; o += kThreads) {
                 const int r = o / A.Wp, col = o - r * A.Wp;
                 const double *vr = (const double *)(Vs + r * LY.RS);
-                double s = 0.0;
-                for (int k = 0; k < A.Dp; ++k) s = fma(vr[k], Td[(int64_t)k * A.Wp + col], s);
+                const double *tc = Td + col;
+                double s4[4] = {0.0, 0.0, 0.0, 0.0};
+                int k = 0;
+                for (; k + 16 <= A.Dp; k += 16) {
+                    double t[16];
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) t[u] = tc[(int64_t)(k + u) * A.Wp];
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) s4[u & 3] = fma(vr[k + u], t[u], s4[u & 3]);
+                }
+                for (; k < A.Dp; ++k) s4[0] = fma(vr[k], tc[(int64_t)k * A.Wp], s4[0]);
+                const double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
                 Cs[r * LY.CSW + col] = s * A.coef + A.logrho64[col];
             }
         } else {
