@@ -1158,9 +1158,46 @@ __global__ __launch_bounds__(kThreads) void pass_kernel(PassArgs A) {
 
         // ---- a3: correlations C and log-weights l' = coef * C + log rho  -> Cs
         if constexpr (P == P_F64) {
+            const double *Td = (const double *)A.Thi;
+            const int nq = BM * A.Wp / kThreads;
+            if (LD && kThreads % A.Wp == 0 && nq * kThreads == BM * A.Wp && nq <= 4) {
+                // every output of a thread lies in one window column (col = tid % Wp, rows
+                // tid / Wp + q kThreads / Wp): one read of the template column serves all of
+                // them; eight reals read at a time (the LDS-staged form only: the register-staged
+                // one has no registers to spare)
+                const int col = tid % A.Wp, r0 = tid / A.Wp, rstep = kThreads / A.Wp;
+                const double *tc = Td + col;
+                double sq[4] = {0.0, 0.0, 0.0, 0.0};
+                int k = 0;
+                for (; k + 8 <= A.Dp; k += 8) {
+                    double t[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) t[u] = tc[(int64_t)(k + u) * A.Wp];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        if (q >= nq) break;
+                        const double *vr = (const double *)(Vs + (r0 + q * rstep) * LY.RS);
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) sq[q] = fma(vr[k + u], t[u], sq[q]);
+                    }
+                }
+                for (; k < A.Dp; ++k) {
+                    const double t = tc[(int64_t)k * A.Wp];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        if (q >= nq) break;
+                        const double *vr = (const double *)(Vs + (r0 + q * rstep) * LY.RS);
+                        sq[q] = fma(vr[k], t, sq[q]);
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (q >= nq) break;
+                    Cs[(r0 + q * rstep) * LY.CSW + col] = sq[q] * A.coef + A.logrho64[col];
+                }
+            } else
             // (the template column is read from global memory 16 reals at a time, all 16 reads
             // issued before the products, which run in four chains added at the end)
-            const double *Td = (const double *)A.Thi;
             for (int o = tid; o < BM * A.Wp; o += kThreads) {
                 const int r = o / A.Wp, col = o - r * A.Wp;
                 const double *vr = (const double *)(Vs + r * LY.RS);
