@@ -15,7 +15,7 @@ def pytest_configure(config):
 
 @pytest.fixture(scope="session")
 def gpu():
-    """Skip unless a GPU is visible; on a GPU machine the HIP library must load (no fallback)."""
+    """Skip unless a GPU is visible; with a GPU present the HIP library must load (no fallback)."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU visible")
